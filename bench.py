@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched AES hot path on one MI355X.
+
+Workload (the single-call form at scale): 65,536 independent 4 KiB pages
+(256 MiB), 16 keys assigned round-robin, uniform random bytes.  One step runs
+the four single calls AES-128 CBC-decrypt, AES-128 CTR (64-bit counter per
+page from 0, random nonce), AES-256 CBC-decrypt and AES-256 CTR over the whole
+buffer.  Each call is a plan launch: the request list was validated, cut into
+work units and uploaded to HBM before the timed region, so data and metadata
+are resident when it starts.
+
+Prints one JSON line: GB/s of payload (10^9 bytes/s) over the timed steps,
+the roofline record of the dominant kernel (HIP events on the launch stream)
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+UNIT_BYTES = 32  # one work-unit record read per tile
+SCHED_BYTES = 512
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--pages", type=int, default=65536)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-pages", type=int, default=65536,
+                    help="pages per run timed on the CPU oracle")
+    ap.add_argument("--per-call-iters", type=int, default=3,
+                    help="iterations of the host-metadata single-call form (0 = skip)")
+    return ap.parse_args()
+
+
+def cpu_baseline(sample_pages: int):
+    """The CPU oracle (all host cores) on the first sample_pages pages of each
+    of the four runs of a step; GB/s of payload."""
+    import numpy as np
+
+    import oracle
+    from synth import workloads
+
+    total = 0
+    secs = 0.0
+    threads = 1
+    for bits in (128, 256):
+        for op in (workloads.OP_CBC_DEC, workloads.OP_CTR):
+            wl = workloads.config2(op, bits, n_pages=sample_pages)
+            inp = wl.data()
+            out = np.empty_like(inp)
+            t0 = time.perf_counter()
+            threads = oracle.batch(inp, out, wl.reqs, wl.keys, wl.key_bits, n_threads=0)
+            secs += time.perf_counter() - t0
+            total += wl.payload_bytes()
+    return {"value": round(total / secs / 1e9, 4), "unit": "GB/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {sample_pages} pages of each of the 4 runs of a step "
+                      f"({total >> 20} MiB), same keys/IVs/bytes, {secs:.1f} s"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build measures the single-GPU hot path "
+              "(pages shard across GPUs with no exchange; see the design notes).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1305_3345_amd import aesgpu
+    from synth import gen, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = aesgpu.Context(0)
+
+    n_pages = args.pages
+    nbytes = n_pages * workloads.PAGE
+    d_in = gen.bytes_torch(0, gen.STREAM_DATA, nbytes, dev)  # same bytes as workloads.data()
+    d_out = torch.empty_like(d_in)
+
+    runs = []  # (name, kernel, plan, d_scheds, payload, units)
+    for bits in (128, 256):
+        for op, kname in ((workloads.OP_CBC_DEC, "cbcdec_tiles"), (workloads.OP_CTR, "ctr_tiles")):
+            wl = workloads.config2(op, bits, n_pages=n_pages)
+            d_s = aesgpu.schedules_to_device(aesgpu.expand_keys(wl.keys, wl.key_bits), dev)
+            plan = aesgpu.Plan(ctx, wl.reqs, wl.keys.shape[0], nbytes)
+            info = plan.info()
+            units = info["n_units_cbc_dec"] + info["n_units_ctr"]
+            runs.append((f"{workloads.OP_NAMES[op]}_{bits}", kname, plan, d_s,
+                         info["payload_bytes"], units, wl))
+    stream = torch.cuda.current_stream()
+
+    def step(events=None):
+        for i, (_, _, plan, d_s, _, _, _) in enumerate(runs):
+            if events is not None:
+                events[i][0].record(stream)
+            plan.launch(d_s, d_in, d_out, stream=stream)
+            if events is not None:
+                events[i][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+           for _ in runs] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(ev[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    payload_step = sum(r[4] for r in runs)
+    value = payload_step * args.steps / elapsed / 1e9
+    per_run = {}
+    per_kernel = {}
+    for i, (name, kname, _, _, payload, units, _) in enumerate(runs):
+        ms = [ev[k][i][0].elapsed_time(ev[k][i][1]) for k in range(args.steps)]
+        avg = sum(ms) / len(ms)
+        algo = 2 * payload + units * UNIT_BYTES + 16 * SCHED_BYTES
+        per_run[name] = {"ms": round(avg, 4), "gbs_payload": round(payload / avg / 1e6, 1),
+                         "hbm_frac": round(algo / avg / 1e6 / HBM_PEAK_GBS, 4)}
+        pk = per_kernel.setdefault(kname, {"ms_total": 0.0, "launches": 0, "algo_bytes": 0})
+        pk["ms_total"] += sum(ms)
+        pk["launches"] += len(ms)
+        pk["algo_bytes"] += algo * len(ms)
+    dom = max(per_kernel, key=lambda k: per_kernel[k]["ms_total"])
+    d = per_kernel[dom]
+    avg_ms = d["ms_total"] / d["launches"]
+    algo_per_launch = d["algo_bytes"] / d["launches"]
+    achieved = algo_per_launch / avg_ms / 1e6
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": f"k_{dom}", "avg_launch_ms": round(avg_ms, 4),
+                "algo_bytes_per_launch": int(algo_per_launch)}
+
+    # Host-metadata single-call form: validation, planning and the unit-table
+    # upload happen inside every call (end-to-end, reported beside the value).
+    per_call = None
+    if args.per_call_iters > 0:
+        t_sum = 0.0
+        for _ in range(args.per_call_iters):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for name, _, _, d_s, _, _, wl in runs:
+                r = wl.reqs
+                fn = aesgpu.ctr_batch if name.startswith("ctr") else aesgpu.cbc_decrypt_batch
+                fn(ctx, d_s, d_in, d_out, r["offset"], r["length"], r["key_idx"], r["iv"])
+            torch.cuda.synchronize()
+            t_sum += time.perf_counter() - t1
+        per_call = {"value": round(payload_step * args.per_call_iters / t_sum / 1e9, 2),
+                    "unit": "GB/s",
+                    "note": "aes_cbc_decrypt_batch / aes_ctr_batch with host request arrays "
+                            "(validation + planning + metadata upload in every call)"}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(min(args.cpu_sample_pages, n_pages))
+
+    line = {
+        "metric": "AES GB/s on 4 KiB pages (batched vs per-call); p50/p99 latency in serving loop",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": f"single-call form at scale: {n_pages} x 4 KiB pages "
+                               f"({nbytes >> 20} MiB), 16 keys round-robin, uniform random bytes; "
+                               "step = AES-128 CBC-dec, AES-128 CTR, AES-256 CBC-dec, AES-256 CTR",
+                   "pages": n_pages, "page_bytes": workloads.PAGE,
+                   "form": "plan launch (unit table resident in HBM)"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "per_run": per_run,
+        "per_call": per_call,
+    }
+    for _, _, plan, _, _, _, _ in runs:
+        plan.close()
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/*
+ * aesgpu.h -- C ABI of the MI355X (gfx950) batched AES library.
+ *
+ * The library runs the data-parallel service of "Augmenting Operating Systems
+ * With the GPU" (Sun and Ricci): AES over many independent page-sized
+ * buffers, offered by the GPU to an OS-kernel-like caller.  Section 3.3 of
+ * the paper implements AES as a GPU service behind the kernel crypto layer;
+ * section 3.2 defines how a caller uses such a service (a buffer in, a buffer
+ * out, a service request, an optional completion callback, then block or
+ * busy-wait); section 2 notes that one launch may carry either one large task
+ * or many small tasks of different callers, and section 3.1 that batching
+ * trades latency for throughput.  The cipher itself is FIPS-197 (AES-128,
+ * -192, -256) in the CBC and CTR modes of NIST SP 800-38A.
+ *
+ * Conventions for every call:
+ *   - Return value: AES_OK (0) or a negative AES_ERR_* code.  No call aborts
+ *     or prints.  Arguments are validated on the host before any HIP call;
+ *     on a validation error nothing is launched and no output byte changes.
+ *   - "d_" pointers are device (HBM) addresses on the context's device; all
+ *     other pointers are host addresses.  Host arrays may be freed as soon as
+ *     the call returns.  Device buffers must stay valid until the work that
+ *     uses them has completed on its stream.
+ *   - hipStream_t arguments are passed as void*; NULL is the default stream.
+ *     Calls that launch work are asynchronous with respect to the host.
+ *   - One context must not be used by two host threads at once.
+ */
+#ifndef AESGPU_H
+#define AESGPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------- status codes */
+enum {
+    AES_OK = 0,
+    AES_ERR_ARG = -1,      /* null pointer, bad enum, zero count where one is needed */
+    AES_ERR_KEYSIZE = -2,  /* key_bits not 128, 192 or 256 */
+    AES_ERR_LENGTH = -3,   /* CBC length not a multiple of 16, or a request >= 4 GiB */
+    AES_ERR_RANGE = -4,    /* offset not a multiple of 16, or offset+length > buf_bytes,
+                              or key index >= number of schedules */
+    AES_ERR_OVERLAP = -5,  /* two requests write overlapping bytes, or in/out partly alias */
+    AES_ERR_DEVICE = -6,   /* a HIP call failed (code in aes_last_hip_error), or the
+                              context has no device */
+    AES_ERR_NOMEM = -7,    /* host or device allocation failed */
+    AES_ERR_AGAIN = -8,    /* serving: ring full or admission cap reached; retry */
+    AES_ERR_TIMEOUT = -9,  /* serving: wait timed out */
+    AES_ERR_STATE = -10    /* object used in a state that does not allow the call */
+};
+
+/* Static description of a status code (never NULL). */
+const char *aes_strerror(int status);
+/* The hipError_t of the last failing HIP call made by this host thread. */
+int aes_last_hip_error(void);
+
+/* ------------------------------------------------------------ key schedules */
+
+/* Expanded key, 512 bytes, plain old data; made by aes_expand_key on the host
+ * and copied by the caller to device memory as an array.
+ *   ek[4*r + c]: round-key word c of round r (FIPS-197 5.2 w[4r+c]); the word's
+ *                four bytes are stored in FIPS byte order, so a little-endian
+ *                32-bit load of ek[i] has w[i]'s first byte in bits 0..7.
+ *   dk[4*r + c]: round key of round r of the equivalent inverse cipher
+ *                (FIPS-197 5.3.5): dk round 0 = w round Nr, dk round r =
+ *                InvMixColumns(w round Nr-r) for 0 < r < Nr, dk round Nr =
+ *                w round 0; same byte layout.
+ * Words beyond round Nr are zero. */
+typedef struct aes_schedule {
+    uint32_t key_bits; /* 128, 192 or 256 */
+    uint32_t nr;       /* 10, 12 or 14 rounds */
+    uint32_t reserved0[2];
+    uint32_t ek[60];
+    uint32_t dk[60];
+    uint32_t reserved1[4];
+} aes_schedule_t;
+
+/* FIPS-197 5.2 KeyExpansion of key (key_bits/8 bytes) into *out.  Pure host
+ * function.  Errors: AES_ERR_ARG (null), AES_ERR_KEYSIZE. */
+int aes_expand_key(const uint8_t *key, uint32_t key_bits, aes_schedule_t *out);
+
+/* ------------------------------------------------------------------ context */
+
+typedef struct aes_ctx aes_ctx_t;
+
+/* AES_DEVICE_NONE makes a host-only context: every call validates and plans
+ * as usual, and any call that would launch work returns AES_ERR_DEVICE. */
+#define AES_DEVICE_NONE (-1)
+
+/* Creates a context on HIP device hip_device (or AES_DEVICE_NONE).  The
+ * context owns the cipher table images in device memory, pinned staging for
+ * request metadata and the tuned launch configuration.
+ * Errors: AES_ERR_ARG, AES_ERR_DEVICE, AES_ERR_NOMEM. */
+int aes_ctx_create(int hip_device, aes_ctx_t **out);
+/* Waits for the context's outstanding work, then frees it.  NULL is a no-op. */
+void aes_ctx_destroy(aes_ctx_t *ctx);
+
+/* ----------------------------------------------------------------- requests */
+
+enum { AES_OP_CBC_ENC = 0, AES_OP_CBC_DEC = 1, AES_OP_CTR = 2 };
+
+/* One service request (paper section 3.2: input buffer, output buffer and a
+ * request naming the service).  Bytes [offset, offset+length) of the input
+ * buffer are transformed into the same range of the output buffer.
+ *   offset: multiple of 16.
+ *   length: bytes, < 2^32; a multiple of 16 for CBC; any value for CTR (a
+ *           final partial block uses the leading keystream bytes); 0 = no-op.
+ *   key_idx: index into the schedule array passed with the call.
+ *   op:     AES_OP_CBC_ENC, AES_OP_CBC_DEC or AES_OP_CTR (CTR encrypts and
+ *           decrypts alike).
+ *   iv:     CBC: the IV.  CTR: the initial counter block T1; bytes 0..7 are a
+ *           nonce and bytes 8..15 a big-endian 64-bit counter that advances by
+ *           one per block modulo 2^64 without carrying into the nonce.
+ * Requests of one call must write pairwise disjoint byte ranges; the input
+ * and output buffers are either the same buffer or do not overlap at all. */
+typedef struct aes_req {
+    uint64_t offset;
+    uint64_t length;
+    uint32_t key_idx;
+    uint32_t op;
+    uint8_t iv[16];
+} aes_req_t;
+
+/* Batched service call (paper sections 2 and 3.3: many independent buffers
+ * in one GPU launch).  d_scheds: device array of n_scheds schedules.
+ * d_in, d_out: device buffers of buf_bytes bytes.  reqs: host array of
+ * n_reqs requests, validated and planned on the host, then copied to the
+ * device through pinned staging before the call returns.  Work is launched on
+ * stream; bytes of d_out outside every request are never written.
+ * Errors: AES_ERR_ARG, AES_ERR_LENGTH, AES_ERR_RANGE, AES_ERR_OVERLAP,
+ * AES_ERR_DEVICE, AES_ERR_NOMEM.  A schedule whose nr is not 10, 12 or 14
+ * leaves its requests' output bytes unwritten. */
+int aes_batch(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+              const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
+              const aes_req_t *reqs, uint64_t n_reqs, void *stream);
+
+/* Single-mode forms of aes_batch with the requests given as parallel host
+ * arrays: offsets[i], lengths[i], key_idx[i] and ivs[16*i .. 16*i+15] form
+ * request i; every request uses the mode the name says (SP 800-38A 6.2 CBC
+ * encryption / decryption, 6.5 CTR).  Same errors as aes_batch. */
+int aes_cbc_encrypt_batch(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+                          const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
+                          const uint64_t *offsets, const uint64_t *lengths,
+                          const uint32_t *key_idx, const uint8_t *ivs, uint64_t n,
+                          void *stream);
+int aes_cbc_decrypt_batch(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+                          const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
+                          const uint64_t *offsets, const uint64_t *lengths,
+                          const uint32_t *key_idx, const uint8_t *ivs, uint64_t n,
+                          void *stream);
+int aes_ctr_batch(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+                  const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
+                  const uint64_t *offsets, const uint64_t *lengths,
+                  const uint32_t *key_idx, const uint8_t *ivs, uint64_t n, void *stream);
+
+/* -------------------------------------------------------------------- plans */
+
+/* A plan is a validated request list cut into work units once and kept in
+ * device memory, so that the same batch shape can be launched many times
+ * (and captured in a HIP graph) with no host planning or metadata copy per
+ * launch -- the "pre-loaded service" idea of paper section 3.1 applied to the
+ * request metadata.  A plan must not be launched on two streams at once. */
+typedef struct aes_plan aes_plan_t;
+
+/* One work unit of a plan, 32 bytes (the device record the kernels read):
+ *   offset, nbytes: the byte range the unit covers.
+ *   meta: bits 0..23 schedule index, bits 24..25 op, bit 26 set when a CBC
+ *         decryption unit takes its predecessor block from the 16 input bytes
+ *         before offset (every tile of a request but the first).
+ *   w: CTR -- nonce bytes 0..3 and 4..7 as little-endian words, then the
+ *      64-bit counter of the unit's first block (w[2] low, w[3] high half);
+ *      CBC -- the IV as four little-endian words (first unit of a request).
+ * CTR and CBC-decryption requests become tiles of the context's tile size
+ * (4096 bytes by default); each CBC-encryption request is one unit (a serial
+ * chain), and chains are ordered longest first. */
+typedef struct aes_unit {
+    uint64_t offset;
+    uint32_t nbytes;
+    uint32_t meta;
+    uint32_t w[4];
+} aes_unit_t;
+
+typedef struct aes_plan_info {
+    uint64_t n_units_cbc_dec;
+    uint64_t n_units_ctr;
+    uint64_t n_chains_cbc_enc;
+    uint64_t payload_bytes; /* sum of request lengths */
+    uint64_t extent_bytes;  /* max(offset + length) */
+    uint32_t tile_bytes;
+    uint32_t reserved;
+} aes_plan_info_t;
+
+/* Validates reqs (same rules as aes_batch) for buffers of buf_bytes bytes and
+ * n_scheds schedules, plans them and uploads the unit table (synchronously).
+ * On a AES_DEVICE_NONE context the plan is host-only (inspectable, not
+ * launchable).  Errors: as aes_batch. */
+int aes_plan_create(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_scheds,
+                    uint64_t buf_bytes, aes_plan_t **out);
+/* Launches a plan on stream over buffers of the plan's buf_bytes.  d_in may
+ * equal d_out (in-place).  Errors: AES_ERR_ARG, AES_ERR_OVERLAP,
+ * AES_ERR_DEVICE. */
+int aes_plan_launch(aes_plan_t *plan, const aes_schedule_t *d_scheds, const uint8_t *d_in,
+                    uint8_t *d_out, void *stream);
+int aes_plan_info(const aes_plan_t *plan, aes_plan_info_t *info);
+/* Copies up to max unit records (CBC-decrypt tiles, then CTR tiles, then
+ * chains) to out and sets *n_out to the plan's total unit count. */
+int aes_plan_units(const aes_plan_t *plan, aes_unit_t *out, uint64_t max, uint64_t *n_out);
+/* Waits for the device to be idle, then frees the plan.  NULL is a no-op. */
+void aes_plan_destroy(aes_plan_t *plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AESGPU_H */

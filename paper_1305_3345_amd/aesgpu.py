@@ -1,0 +1,282 @@
+"""Thin ctypes binding of libaesgpu.so (the C ABI declared in include/aesgpu.h).
+
+Argument marshalling only: every cipher step runs in the library's HIP
+kernels.  Device buffers are torch tensors (their ``data_ptr()`` crosses the
+boundary) or raw integer device addresses; streams are torch streams or raw
+``hipStream_t`` integers (default: torch's current stream).  The library must
+be built (``python -m paper_1305_3345_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+try:  # torch first: the library then binds to the HIP runtime torch has loaded
+    import torch
+except ImportError:  # host-only use (validation, planning) without torch
+    torch = None
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libaesgpu.so")
+
+AES_OK = 0
+AES_ERR_ARG = -1
+AES_ERR_KEYSIZE = -2
+AES_ERR_LENGTH = -3
+AES_ERR_RANGE = -4
+AES_ERR_OVERLAP = -5
+AES_ERR_DEVICE = -6
+AES_ERR_NOMEM = -7
+AES_ERR_AGAIN = -8
+AES_ERR_TIMEOUT = -9
+AES_ERR_STATE = -10
+
+AES_OP_CBC_ENC = 0
+AES_OP_CBC_DEC = 1
+AES_OP_CTR = 2
+AES_DEVICE_NONE = -1
+
+SCHED_DTYPE = np.dtype([("key_bits", "<u4"), ("nr", "<u4"), ("reserved0", "<u4", (2,)),
+                        ("ek", "<u4", (60,)), ("dk", "<u4", (60,)), ("reserved1", "<u4", (4,))])
+REQ_DTYPE = np.dtype([("offset", "<u8"), ("length", "<u8"), ("key_idx", "<u4"),
+                      ("op", "<u4"), ("iv", "u1", (16,))])
+UNIT_DTYPE = np.dtype([("offset", "<u8"), ("nbytes", "<u4"), ("meta", "<u4"),
+                       ("w", "<u4", (4,))])
+PLAN_INFO_DTYPE = np.dtype([("n_units_cbc_dec", "<u8"), ("n_units_ctr", "<u8"),
+                            ("n_chains_cbc_enc", "<u8"), ("payload_bytes", "<u8"),
+                            ("extent_bytes", "<u8"), ("tile_bytes", "<u4"),
+                            ("reserved", "<u4")])
+assert SCHED_DTYPE.itemsize == 512 and REQ_DTYPE.itemsize == 40 and UNIT_DTYPE.itemsize == 32
+
+_lib = None
+_lock = threading.Lock()
+
+
+class AesError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = lib().aes_strerror(status).decode()
+        if status == AES_ERR_DEVICE:
+            msg += f" (hipError {lib().aes_last_hip_error()})"
+        super().__init__(f"{where}: {msg} [{status}]")
+
+
+def lib():
+    """Loads libaesgpu.so once; raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1305_3345_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        p = ctypes.c_void_p
+        u32, u64, i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+        sig = {
+            "aes_strerror": (ctypes.c_char_p, [i32]),
+            "aes_last_hip_error": (i32, []),
+            "aes_expand_key": (i32, [p, u32, p]),
+            "aes_ctx_create": (i32, [i32, ctypes.POINTER(p)]),
+            "aes_ctx_destroy": (None, [p]),
+            "aes_batch": (i32, [p, p, u32, p, p, u64, p, u64, p]),
+            "aes_cbc_encrypt_batch": (i32, [p, p, u32, p, p, u64, p, p, p, p, u64, p]),
+            "aes_cbc_decrypt_batch": (i32, [p, p, u32, p, p, u64, p, p, p, p, u64, p]),
+            "aes_ctr_batch": (i32, [p, p, u32, p, p, u64, p, p, p, p, u64, p]),
+            "aes_plan_create": (i32, [p, p, u64, u32, u64, ctypes.POINTER(p)]),
+            "aes_plan_launch": (i32, [p, p, p, p, p]),
+            "aes_plan_info": (i32, [p, p]),
+            "aes_plan_units": (i32, [p, p, u64, ctypes.POINTER(u64)]),
+            "aes_plan_destroy": (None, [p]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+        return L
+
+
+def _check(status: int, where: str):
+    if status != AES_OK:
+        raise AesError(status, where)
+
+
+def _ptr(x) -> int:
+    """Device/host address of a tensor, numpy array or raw integer (0 for None)."""
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    if torch is not None and isinstance(x, torch.Tensor):
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    raise TypeError(f"cannot take the address of {type(x)}")
+
+
+def _nbytes(x) -> int:
+    if torch is not None and isinstance(x, torch.Tensor):
+        return x.numel() * x.element_size()
+    if isinstance(x, np.ndarray):
+        return x.nbytes
+    raise TypeError("buffer size needed")
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        if torch is not None and torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+        return 0
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ----------------------------------------------------------------- key setup
+
+def expand_key(key, key_bits: int) -> np.ndarray:
+    """aes_expand_key: one schedule record (SCHED_DTYPE) for key_bits/8 key bytes."""
+    k = np.ascontiguousarray(np.frombuffer(bytes(key), np.uint8) if not isinstance(key, np.ndarray)
+                             else key, dtype=np.uint8)
+    out = np.zeros(1, SCHED_DTYPE)
+    _check(lib().aes_expand_key(k.ctypes.data, key_bits, out.ctypes.data), "aes_expand_key")
+    return out[0]
+
+
+def expand_keys(keys: np.ndarray, key_bits) -> np.ndarray:
+    """Schedules for an (n, >=32) uint8 key array; key_bits per key or scalar."""
+    kb = np.broadcast_to(np.asarray(key_bits, np.uint32), (keys.shape[0],))
+    out = np.zeros(keys.shape[0], SCHED_DTYPE)
+    for i in range(keys.shape[0]):
+        out[i] = expand_key(np.ascontiguousarray(keys[i, : kb[i] // 8]), int(kb[i]))
+    return out
+
+
+def schedules_to_device(scheds: np.ndarray, device="cuda"):
+    """Copies schedule records to a device uint8 tensor (512 bytes each)."""
+    host = torch.from_numpy(np.ascontiguousarray(scheds).view(np.uint8).copy())
+    return host.to(device)
+
+
+# ------------------------------------------------------------------- context
+
+class Context:
+    """aes_ctx_create / aes_ctx_destroy.  device=AES_DEVICE_NONE gives a host-only context."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().aes_ctx_create(device, ctypes.byref(h)), "aes_ctx_create")
+        self.handle = h.value
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib().aes_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _sched_count(d_scheds, n_scheds):
+    if n_scheds is not None:
+        return n_scheds
+    return _nbytes(d_scheds) // SCHED_DTYPE.itemsize
+
+
+def batch(ctx: Context, d_scheds, d_in, d_out, reqs: np.ndarray, buf_bytes: int | None = None,
+          n_scheds: int | None = None, stream=None):
+    """aes_batch over a REQ_DTYPE request array."""
+    reqs = np.ascontiguousarray(reqs, dtype=REQ_DTYPE)
+    bb = _nbytes(d_in) if buf_bytes is None else buf_bytes
+    _check(lib().aes_batch(ctx.handle, _ptr(d_scheds), _sched_count(d_scheds, n_scheds),
+                           _ptr(d_in), _ptr(d_out), bb, reqs.ctypes.data, reqs.size,
+                           _stream(stream)), "aes_batch")
+
+
+def _single(name, ctx, d_scheds, d_in, d_out, offsets, lengths, key_idx, ivs, buf_bytes,
+            n_scheds, stream):
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    ln = np.ascontiguousarray(lengths, dtype=np.uint64)
+    ki = np.ascontiguousarray(key_idx, dtype=np.uint32)
+    iv = np.ascontiguousarray(ivs, dtype=np.uint8).reshape(-1)
+    n = off.size
+    if ln.size != n or ki.size != n or iv.size != 16 * n:
+        raise ValueError("offsets, lengths, key_idx and ivs must describe the same requests")
+    bb = _nbytes(d_in) if buf_bytes is None else buf_bytes
+    _check(getattr(lib(), name)(ctx.handle, _ptr(d_scheds), _sched_count(d_scheds, n_scheds),
+                                _ptr(d_in), _ptr(d_out), bb, off.ctypes.data, ln.ctypes.data,
+                                ki.ctypes.data, iv.ctypes.data, n, _stream(stream)), name)
+
+
+def cbc_encrypt_batch(ctx, d_scheds, d_in, d_out, offsets, lengths, key_idx, ivs,
+                      buf_bytes=None, n_scheds=None, stream=None):
+    _single("aes_cbc_encrypt_batch", ctx, d_scheds, d_in, d_out, offsets, lengths, key_idx, ivs,
+            buf_bytes, n_scheds, stream)
+
+
+def cbc_decrypt_batch(ctx, d_scheds, d_in, d_out, offsets, lengths, key_idx, ivs,
+                      buf_bytes=None, n_scheds=None, stream=None):
+    _single("aes_cbc_decrypt_batch", ctx, d_scheds, d_in, d_out, offsets, lengths, key_idx, ivs,
+            buf_bytes, n_scheds, stream)
+
+
+def ctr_batch(ctx, d_scheds, d_in, d_out, offsets, lengths, key_idx, ivs,
+              buf_bytes=None, n_scheds=None, stream=None):
+    _single("aes_ctr_batch", ctx, d_scheds, d_in, d_out, offsets, lengths, key_idx, ivs,
+            buf_bytes, n_scheds, stream)
+
+
+# --------------------------------------------------------------------- plans
+
+class Plan:
+    """aes_plan_create / launch / info / units / destroy."""
+
+    def __init__(self, ctx: Context, reqs: np.ndarray, n_scheds: int, buf_bytes: int):
+        reqs = np.ascontiguousarray(reqs, dtype=REQ_DTYPE)
+        h = ctypes.c_void_p()
+        _check(lib().aes_plan_create(ctx.handle, reqs.ctypes.data, reqs.size, n_scheds,
+                                     buf_bytes, ctypes.byref(h)), "aes_plan_create")
+        self.handle = h.value
+        self.ctx = ctx  # keeps the context alive
+
+    def launch(self, d_scheds, d_in, d_out, stream=None):
+        _check(lib().aes_plan_launch(self.handle, _ptr(d_scheds), _ptr(d_in), _ptr(d_out),
+                                     _stream(stream)), "aes_plan_launch")
+
+    def info(self) -> dict:
+        out = np.zeros(1, PLAN_INFO_DTYPE)
+        _check(lib().aes_plan_info(self.handle, out.ctypes.data), "aes_plan_info")
+        return {k: int(out[0][k]) for k in PLAN_INFO_DTYPE.names if k != "reserved"}
+
+    def units(self) -> np.ndarray:
+        n = ctypes.c_uint64()
+        _check(lib().aes_plan_units(self.handle, None, 0, ctypes.byref(n)), "aes_plan_units")
+        out = np.zeros(n.value, UNIT_DTYPE)
+        _check(lib().aes_plan_units(self.handle, out.ctypes.data if n.value else None, n.value,
+                                    ctypes.byref(n)), "aes_plan_units")
+        return out
+
+    def close(self):
+        if self.handle:
+            lib().aes_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,604 @@
+// aes_abi.cpp -- the C ABI: validation, planning, contexts, plans, launches.
+//
+// A call follows the service-request path of the paper (section 3.2): the
+// caller hands over input and output buffers and a request list; the library
+// checks every request on the host, cuts the requests into work units
+// (section 2: one launch carries one large task or many small tasks), copies
+// the unit table to the device through pinned staging and launches the round
+// kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+using namespace aesgpu;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_fail(hipError_t e) {
+    g_last_hip = (int)e;
+    return AES_ERR_DEVICE;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return hip_fail(e_);                                                                   \
+    } while (0)
+
+constexpr uint64_t MAX_REQ_BYTES = (1ull << 32) - 16;
+constexpr uint32_t DEFAULT_TILE = 4096;
+
+// ------------------------------------------------------------- validation
+
+// Checks one request list against buffer size and schedule count, and that
+// the written byte ranges are pairwise disjoint.
+int validate(const aes_req_t *reqs, uint64_t n, uint32_t n_scheds, uint64_t buf_bytes) {
+    if (n && !reqs)
+        return AES_ERR_ARG;
+    bool sorted = true;
+    uint64_t last_off = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        const aes_req_t &r = reqs[i];
+        if (r.op > AES_OP_CTR)
+            return AES_ERR_ARG;
+        if (r.length > MAX_REQ_BYTES)
+            return AES_ERR_LENGTH;
+        if (r.op != AES_OP_CTR && (r.length & 15))
+            return AES_ERR_LENGTH;
+        if ((r.offset & 15) || r.offset > buf_bytes || r.length > buf_bytes - r.offset)
+            return AES_ERR_RANGE;
+        if (r.key_idx >= n_scheds || r.key_idx >= MAX_KEYS)
+            return AES_ERR_RANGE;
+        if (r.length) {
+            if (r.offset < last_off)
+                sorted = false;
+            last_off = r.offset;
+        }
+    }
+    // Disjointness: a linear scan when the requests come in offset order
+    // (the common case), else a sort of (offset, end) pairs.
+    if (sorted) {
+        uint64_t end = 0;
+        bool any = false;
+        for (uint64_t i = 0; i < n; i++) {
+            if (!reqs[i].length)
+                continue;
+            if (any && reqs[i].offset < end)
+                return AES_ERR_OVERLAP;
+            end = reqs[i].offset + reqs[i].length;
+            any = true;
+        }
+        return AES_OK;
+    }
+    std::vector<std::pair<uint64_t, uint64_t>> ranges;
+    try {
+        ranges.reserve(n);
+    } catch (const std::bad_alloc &) {
+        return AES_ERR_NOMEM;
+    }
+    for (uint64_t i = 0; i < n; i++)
+        if (reqs[i].length)
+            ranges.emplace_back(reqs[i].offset, reqs[i].offset + reqs[i].length);
+    std::sort(ranges.begin(), ranges.end());
+    for (size_t i = 1; i < ranges.size(); i++)
+        if (ranges[i].first < ranges[i - 1].second)
+            return AES_ERR_OVERLAP;
+    return AES_OK;
+}
+
+int check_buffers(const uint8_t *d_in, const uint8_t *d_out, uint64_t buf_bytes, uint64_t n,
+                  const void *d_scheds) {
+    if (!n)
+        return AES_OK;
+    if (!d_in || !d_out || !d_scheds)
+        return AES_ERR_ARG;
+    if (d_in != d_out) {
+        const uintptr_t a = (uintptr_t)d_in, b = (uintptr_t)d_out;
+        if (a < b + buf_bytes && b < a + buf_bytes)
+            return AES_ERR_OVERLAP;
+    }
+    return AES_OK;
+}
+
+// ---------------------------------------------------------------- planner
+
+inline uint32_t le32(const uint8_t *p) {
+    return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
+}
+
+inline uint64_t be64(const uint8_t *p) {
+    uint64_t v = 0;
+    for (int i = 0; i < 8; i++)
+        v = (v << 8) | p[i];
+    return v;
+}
+
+struct Planned {
+    std::vector<Unit> dec;     // CBC-decrypt tiles
+    std::vector<Unit> ctr;     // CTR tiles
+    std::vector<Unit> chains;  // CBC-encrypt chains, longest first
+    uint64_t payload = 0;
+    uint64_t extent = 0;
+    bool dec_has_pred_in = false;
+};
+
+// Cuts every request into units: CTR and CBC-decrypt into tile_bytes tiles
+// (a multiple of 16), CBC-encrypt into one chain each.
+int plan_units(const aes_req_t *reqs, uint64_t n, uint32_t tile_bytes, Planned &p) {
+    try {
+        uint64_t n_tiles_ctr = 0, n_tiles_dec = 0, n_chain = 0;
+        for (uint64_t i = 0; i < n; i++) {
+            const uint64_t t = (reqs[i].length + tile_bytes - 1) / tile_bytes;
+            if (reqs[i].op == AES_OP_CTR)
+                n_tiles_ctr += t;
+            else if (reqs[i].op == AES_OP_CBC_DEC)
+                n_tiles_dec += t;
+            else if (reqs[i].length)
+                n_chain++;
+        }
+        if (n_tiles_ctr >= (1ull << 32) || n_tiles_dec >= (1ull << 32) || n_chain >= (1ull << 32))
+            return AES_ERR_RANGE;
+        p.ctr.reserve(n_tiles_ctr);
+        p.dec.reserve(n_tiles_dec);
+        p.chains.reserve(n_chain);
+        for (uint64_t i = 0; i < n; i++) {
+            const aes_req_t &r = reqs[i];
+            if (!r.length)
+                continue;
+            p.payload += r.length;
+            p.extent = std::max(p.extent, r.offset + r.length);
+            const uint32_t meta_base = r.key_idx | (r.op << META_OP_SHIFT);
+            if (r.op == AES_OP_CBC_ENC) {
+                Unit u;
+                u.off = r.offset;
+                u.nbytes = (uint32_t)r.length;
+                u.meta = meta_base;
+                for (int w = 0; w < 4; w++)
+                    u.w[w] = le32(r.iv + 4 * w);
+                p.chains.push_back(u);
+                continue;
+            }
+            const uint64_t ctr0 = be64(r.iv + 8);
+            for (uint64_t pos = 0; pos < r.length; pos += tile_bytes) {
+                Unit u;
+                u.off = r.offset + pos;
+                u.nbytes = (uint32_t)std::min<uint64_t>(tile_bytes, r.length - pos);
+                u.meta = meta_base;
+                if (r.op == AES_OP_CTR) {
+                    const uint64_t c = ctr0 + pos / 16;  // mod 2^64, nonce untouched
+                    u.w[0] = le32(r.iv);
+                    u.w[1] = le32(r.iv + 4);
+                    u.w[2] = (uint32_t)c;
+                    u.w[3] = (uint32_t)(c >> 32);
+                    p.ctr.push_back(u);
+                } else {
+                    if (pos == 0) {
+                        for (int w = 0; w < 4; w++)
+                            u.w[w] = le32(r.iv + 4 * w);
+                    } else {
+                        u.meta |= FLAG_PRED_IN;
+                        u.w[0] = u.w[1] = u.w[2] = u.w[3] = 0;
+                        p.dec_has_pred_in = true;
+                    }
+                    p.dec.push_back(u);
+                }
+            }
+        }
+        // Longest chain first: a chain's lane finishes last, so the longest
+        // ones start first and neighbouring lanes get similar lengths.
+        std::stable_sort(p.chains.begin(), p.chains.end(),
+                         [](const Unit &a, const Unit &b) { return a.nbytes > b.nbytes; });
+    } catch (const std::bad_alloc &) {
+        return AES_ERR_NOMEM;
+    }
+    return AES_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- context
+
+struct Slot {
+    void *h_stage = nullptr;  // pinned host staging for the unit table
+    size_t h_cap = 0;
+    void *d_units = nullptr;  // device unit table + in-place predecessor snapshots
+    size_t d_cap = 0;
+    hipEvent_t ev = nullptr;  // recorded after the last launch that used the slot
+    bool ev_pending = false;
+};
+
+struct aes_ctx {
+    int device = AES_DEVICE_NONE;
+    int n_cu = 0;
+    uint32_t *d_timg = nullptr;
+    static constexpr int N_SLOTS = 4;
+    Slot slots[N_SLOTS];
+    int next_slot = 0;
+    uint32_t tile_bytes = DEFAULT_TILE;
+    TileLaunch tile_ctr, tile_dec;
+    ChainLaunch chain;
+};
+
+struct aes_plan {
+    aes_ctx *ctx = nullptr;
+    Planned p;
+    uint32_t n_scheds = 0;
+    uint64_t buf_bytes = 0;
+    void *d_units = nullptr;  // [dec | ctr | chains] units, then dec predecessor snapshots
+    size_t n_dec = 0, n_ctr = 0, n_chain = 0;
+};
+
+namespace {
+
+size_t units_bytes(size_t n_dec, size_t n_ctr, size_t n_chain) {
+    return (n_dec + n_ctr + n_chain) * sizeof(Unit) + n_dec * 16;
+}
+
+// Launches the kernels of one planned batch whose unit table is at d_units.
+int launch_planned(aes_ctx *ctx, void *d_units, size_t n_dec, size_t n_ctr, size_t n_chain,
+                   bool pred_in, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+                   const uint8_t *d_in, uint8_t *d_out, void *stream) {
+    Unit *u = (Unit *)d_units;
+    Unit *u_dec = u;
+    Unit *u_ctr = u + n_dec;
+    Unit *u_chain = u + n_dec + n_ctr;
+    void *d_preds = nullptr;
+    int e;
+    if (n_dec && pred_in && d_in == d_out) {
+        d_preds = (void *)(u + n_dec + n_ctr + n_chain);
+        if ((e = launch_snapshot_preds(u_dec, (uint32_t)n_dec, d_in, d_preds, stream)))
+            return hip_fail((hipError_t)e);
+    }
+    if ((e = launch_cbcdec_tiles(u_dec, (uint32_t)n_dec, d_scheds, n_scheds, ctx->d_timg, d_preds,
+                                 d_in, d_out, ctx->tile_dec, ctx->n_cu, stream)))
+        return hip_fail((hipError_t)e);
+    if ((e = launch_ctr_tiles(u_ctr, (uint32_t)n_ctr, d_scheds, n_scheds, ctx->d_timg, d_in, d_out,
+                              ctx->tile_ctr, ctx->n_cu, stream)))
+        return hip_fail((hipError_t)e);
+    if ((e = launch_cbcenc_chains(u_chain, (uint32_t)n_chain, d_scheds, n_scheds, ctx->d_timg,
+                                  d_in, d_out, ctx->chain, ctx->n_cu, stream)))
+        return hip_fail((hipError_t)e);
+    return AES_OK;
+}
+
+void pack_units(const Planned &p, void *dst) {
+    Unit *u = (Unit *)dst;
+    if (!p.dec.empty())
+        memcpy(u, p.dec.data(), p.dec.size() * sizeof(Unit));
+    u += p.dec.size();
+    if (!p.ctr.empty())
+        memcpy(u, p.ctr.data(), p.ctr.size() * sizeof(Unit));
+    u += p.ctr.size();
+    if (!p.chains.empty())
+        memcpy(u, p.chains.data(), p.chains.size() * sizeof(Unit));
+}
+
+int run_batch(aes_ctx *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+              const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes, const aes_req_t *reqs,
+              uint64_t n, void *stream) {
+    if (!ctx)
+        return AES_ERR_ARG;
+    int st = check_buffers(d_in, d_out, buf_bytes, n, d_scheds);
+    if (st)
+        return st;
+    if ((st = validate(reqs, n, n_scheds, buf_bytes)))
+        return st;
+    Planned p;
+    if ((st = plan_units(reqs, n, ctx->tile_bytes, p)))
+        return st;
+    if (!p.payload)
+        return AES_OK;
+    if (ctx->device == AES_DEVICE_NONE)
+        return AES_ERR_DEVICE;
+    HIP_TRY(hipSetDevice(ctx->device));
+    Slot &s = ctx->slots[ctx->next_slot];
+    ctx->next_slot = (ctx->next_slot + 1) % aes_ctx::N_SLOTS;
+    if (s.ev_pending) {
+        HIP_TRY(hipEventSynchronize(s.ev));
+        s.ev_pending = false;
+    }
+    const size_t ubytes = (p.dec.size() + p.ctr.size() + p.chains.size()) * sizeof(Unit);
+    const size_t need = units_bytes(p.dec.size(), p.ctr.size(), p.chains.size());
+    if (s.h_cap < ubytes) {
+        if (s.h_stage)
+            (void)hipHostFree(s.h_stage);
+        s.h_stage = nullptr;
+        s.h_cap = 0;
+        if (hipHostMalloc(&s.h_stage, ubytes, hipHostMallocDefault) != hipSuccess)
+            return AES_ERR_NOMEM;
+        s.h_cap = ubytes;
+    }
+    if (s.d_cap < need) {
+        if (s.d_units)
+            (void)hipFree(s.d_units);
+        s.d_units = nullptr;
+        s.d_cap = 0;
+        if (hipMalloc(&s.d_units, need) != hipSuccess)
+            return AES_ERR_NOMEM;
+        s.d_cap = need;
+    }
+    pack_units(p, s.h_stage);
+    HIP_TRY(hipMemcpyAsync(s.d_units, s.h_stage, ubytes, hipMemcpyHostToDevice,
+                           (hipStream_t)stream));
+    st = launch_planned(ctx, s.d_units, p.dec.size(), p.ctr.size(), p.chains.size(),
+                        p.dec_has_pred_in, d_scheds, n_scheds, d_in, d_out, stream);
+    if (st)
+        return st;
+    HIP_TRY(hipEventRecord(s.ev, (hipStream_t)stream));
+    s.ev_pending = true;
+    return AES_OK;
+}
+
+int single_mode(uint32_t op, aes_ctx *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+                const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes, const uint64_t *offsets,
+                const uint64_t *lengths, const uint32_t *key_idx, const uint8_t *ivs, uint64_t n,
+                void *stream) {
+    if (!ctx)
+        return AES_ERR_ARG;
+    if (n && (!offsets || !lengths || !key_idx || !ivs))
+        return AES_ERR_ARG;
+    std::vector<aes_req_t> reqs;
+    try {
+        reqs.resize(n);
+    } catch (const std::bad_alloc &) {
+        return AES_ERR_NOMEM;
+    }
+    for (uint64_t i = 0; i < n; i++) {
+        reqs[i].offset = offsets[i];
+        reqs[i].length = lengths[i];
+        reqs[i].key_idx = key_idx[i];
+        reqs[i].op = op;
+        memcpy(reqs[i].iv, ivs + 16 * i, 16);
+    }
+    return run_batch(ctx, d_scheds, n_scheds, d_in, d_out, buf_bytes, reqs.data(), n, stream);
+}
+
+}  // namespace
+
+// ============================================================ exported API
+
+extern "C" {
+
+const char *aes_strerror(int status) {
+    switch (status) {
+    case AES_OK: return "ok";
+    case AES_ERR_ARG: return "invalid argument";
+    case AES_ERR_KEYSIZE: return "key size must be 128, 192 or 256 bits";
+    case AES_ERR_LENGTH: return "bad length (CBC needs whole 16-byte blocks; requests < 4 GiB)";
+    case AES_ERR_RANGE: return "offset, range or key index out of bounds";
+    case AES_ERR_OVERLAP: return "requests or buffers overlap";
+    case AES_ERR_DEVICE: return "HIP device error or no device";
+    case AES_ERR_NOMEM: return "out of memory";
+    case AES_ERR_AGAIN: return "resource temporarily unavailable";
+    case AES_ERR_TIMEOUT: return "timed out";
+    case AES_ERR_STATE: return "invalid state for this call";
+    default: return "unknown status";
+    }
+}
+
+int aes_last_hip_error(void) { return g_last_hip; }
+
+int aes_expand_key(const uint8_t *key, uint32_t key_bits, aes_schedule_t *out) {
+    return expand_key(key, key_bits, out);
+}
+
+int aes_ctx_create(int hip_device, aes_ctx_t **out) {
+    if (!out)
+        return AES_ERR_ARG;
+    *out = nullptr;
+    if (hip_device < AES_DEVICE_NONE)
+        return AES_ERR_ARG;
+    aes_ctx *ctx = new (std::nothrow) aes_ctx();
+    if (!ctx)
+        return AES_ERR_NOMEM;
+    ctx->device = hip_device;
+    if (hip_device != AES_DEVICE_NONE) {
+        int ndev = 0;
+        hipError_t e = hipGetDeviceCount(&ndev);
+        if (e != hipSuccess || hip_device >= ndev) {
+            delete ctx;
+            return hip_fail(e != hipSuccess ? e : hipErrorInvalidDevice);
+        }
+        hipDeviceProp_t prop;
+        if ((e = hipSetDevice(hip_device)) != hipSuccess ||
+            (e = hipGetDeviceProperties(&prop, hip_device)) != hipSuccess) {
+            delete ctx;
+            return hip_fail(e);
+        }
+        ctx->n_cu = prop.multiProcessorCount;
+        uint32_t img[TIMG_WORDS];
+        make_table_image(img);
+        if (hipMalloc((void **)&ctx->d_timg, sizeof(img)) != hipSuccess) {
+            delete ctx;
+            return AES_ERR_NOMEM;
+        }
+        if ((e = hipMemcpy(ctx->d_timg, img, sizeof(img), hipMemcpyHostToDevice)) != hipSuccess) {
+            (void)hipFree(ctx->d_timg);
+            delete ctx;
+            return hip_fail(e);
+        }
+        for (Slot &s : ctx->slots) {
+            if ((e = hipEventCreateWithFlags(&s.ev, hipEventDisableTiming)) != hipSuccess) {
+                aes_ctx_destroy(ctx);
+                return hip_fail(e);
+            }
+        }
+    }
+    *out = ctx;
+    return AES_OK;
+}
+
+void aes_ctx_destroy(aes_ctx_t *ctx) {
+    if (!ctx)
+        return;
+    if (ctx->device != AES_DEVICE_NONE) {
+        (void)hipSetDevice(ctx->device);
+        for (Slot &s : ctx->slots) {
+            if (s.ev) {
+                if (s.ev_pending)
+                    (void)hipEventSynchronize(s.ev);
+                (void)hipEventDestroy(s.ev);
+            }
+            if (s.h_stage)
+                (void)hipHostFree(s.h_stage);
+            if (s.d_units)
+                (void)hipFree(s.d_units);
+        }
+        if (ctx->d_timg)
+            (void)hipFree(ctx->d_timg);
+    }
+    delete ctx;
+}
+
+int aes_batch(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+              const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes, const aes_req_t *reqs,
+              uint64_t n_reqs, void *stream) {
+    return run_batch(ctx, d_scheds, n_scheds, d_in, d_out, buf_bytes, reqs, n_reqs, stream);
+}
+
+int aes_cbc_encrypt_batch(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+                          const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
+                          const uint64_t *offsets, const uint64_t *lengths,
+                          const uint32_t *key_idx, const uint8_t *ivs, uint64_t n, void *stream) {
+    return single_mode(AES_OP_CBC_ENC, ctx, d_scheds, n_scheds, d_in, d_out, buf_bytes, offsets,
+                       lengths, key_idx, ivs, n, stream);
+}
+
+int aes_cbc_decrypt_batch(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+                          const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
+                          const uint64_t *offsets, const uint64_t *lengths,
+                          const uint32_t *key_idx, const uint8_t *ivs, uint64_t n, void *stream) {
+    return single_mode(AES_OP_CBC_DEC, ctx, d_scheds, n_scheds, d_in, d_out, buf_bytes, offsets,
+                       lengths, key_idx, ivs, n, stream);
+}
+
+int aes_ctr_batch(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+                  const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
+                  const uint64_t *offsets, const uint64_t *lengths, const uint32_t *key_idx,
+                  const uint8_t *ivs, uint64_t n, void *stream) {
+    return single_mode(AES_OP_CTR, ctx, d_scheds, n_scheds, d_in, d_out, buf_bytes, offsets,
+                       lengths, key_idx, ivs, n, stream);
+}
+
+// ------------------------------------------------------------------ plans
+
+int aes_plan_create(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n, uint32_t n_scheds,
+                    uint64_t buf_bytes, aes_plan_t **out) {
+    if (!ctx || !out)
+        return AES_ERR_ARG;
+    *out = nullptr;
+    int st = validate(reqs, n, n_scheds, buf_bytes);
+    if (st)
+        return st;
+    aes_plan *pl = new (std::nothrow) aes_plan();
+    if (!pl)
+        return AES_ERR_NOMEM;
+    pl->ctx = ctx;
+    pl->n_scheds = n_scheds;
+    pl->buf_bytes = buf_bytes;
+    if ((st = plan_units(reqs, n, ctx->tile_bytes, pl->p))) {
+        delete pl;
+        return st;
+    }
+    pl->n_dec = pl->p.dec.size();
+    pl->n_ctr = pl->p.ctr.size();
+    pl->n_chain = pl->p.chains.size();
+    if (ctx->device != AES_DEVICE_NONE && pl->p.payload) {
+        hipError_t e;
+        const size_t need = units_bytes(pl->n_dec, pl->n_ctr, pl->n_chain);
+        const size_t ubytes = (pl->n_dec + pl->n_ctr + pl->n_chain) * sizeof(Unit);
+        std::vector<Unit> host;
+        try {
+            host.resize(pl->n_dec + pl->n_ctr + pl->n_chain);
+        } catch (const std::bad_alloc &) {
+            delete pl;
+            return AES_ERR_NOMEM;
+        }
+        pack_units(pl->p, host.data());
+        if ((e = hipSetDevice(ctx->device)) != hipSuccess) {
+            delete pl;
+            return hip_fail(e);
+        }
+        if (hipMalloc(&pl->d_units, need) != hipSuccess) {
+            delete pl;
+            return AES_ERR_NOMEM;
+        }
+        if ((e = hipMemcpy(pl->d_units, host.data(), ubytes, hipMemcpyHostToDevice)) !=
+            hipSuccess) {
+            (void)hipFree(pl->d_units);
+            delete pl;
+            return hip_fail(e);
+        }
+    }
+    *out = pl;
+    return AES_OK;
+}
+
+int aes_plan_launch(aes_plan_t *plan, const aes_schedule_t *d_scheds, const uint8_t *d_in,
+                    uint8_t *d_out, void *stream) {
+    if (!plan)
+        return AES_ERR_ARG;
+    const uint64_t n = plan->n_dec + plan->n_ctr + plan->n_chain;
+    int st = check_buffers(d_in, d_out, plan->buf_bytes, n, d_scheds);
+    if (st)
+        return st;
+    if (!plan->p.payload)
+        return AES_OK;
+    aes_ctx *ctx = plan->ctx;
+    if (ctx->device == AES_DEVICE_NONE)
+        return AES_ERR_DEVICE;
+    HIP_TRY(hipSetDevice(ctx->device));
+    return launch_planned(ctx, plan->d_units, plan->n_dec, plan->n_ctr, plan->n_chain,
+                          plan->p.dec_has_pred_in, d_scheds, plan->n_scheds, d_in, d_out, stream);
+}
+
+int aes_plan_info(const aes_plan_t *plan, aes_plan_info_t *info) {
+    if (!plan || !info)
+        return AES_ERR_ARG;
+    memset(info, 0, sizeof(*info));
+    info->n_units_cbc_dec = plan->n_dec;
+    info->n_units_ctr = plan->n_ctr;
+    info->n_chains_cbc_enc = plan->n_chain;
+    info->payload_bytes = plan->p.payload;
+    info->extent_bytes = plan->p.extent;
+    info->tile_bytes = plan->ctx->tile_bytes;
+    return AES_OK;
+}
+
+int aes_plan_units(const aes_plan_t *plan, aes_unit_t *out, uint64_t max, uint64_t *n_out) {
+    if (!plan || !n_out || (max && !out))
+        return AES_ERR_ARG;
+    static_assert(sizeof(aes_unit_t) == sizeof(Unit), "unit record layout");
+    const uint64_t total = plan->n_dec + plan->n_ctr + plan->n_chain;
+    *n_out = total;
+    uint64_t k = 0;
+    for (const auto *v : {&plan->p.dec, &plan->p.ctr, &plan->p.chains})
+        for (const Unit &u : *v) {
+            if (k >= max)
+                return AES_OK;
+            memcpy(&out[k++], &u, sizeof(Unit));
+        }
+    return AES_OK;
+}
+
+void aes_plan_destroy(aes_plan_t *plan) {
+    if (!plan)
+        return;
+    if (plan->d_units) {
+        (void)hipSetDevice(plan->ctx->device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(plan->d_units);
+    }
+    delete plan;
+}
+
+}  // extern "C"

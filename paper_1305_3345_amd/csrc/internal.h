@@ -1,0 +1,70 @@
+// internal.h -- structures shared by the host planner and the HIP kernels.
+#pragma once
+
+#include <stdint.h>
+
+#include "aesgpu.h"
+
+namespace aesgpu {
+
+// A work unit, 32 bytes, in device memory.  The planner cuts CTR and CBC
+// decryption requests into tiles (many units per request, run in parallel)
+// and gives each CBC encryption request one unit (a serial chain).
+struct Unit {
+    uint64_t off;     // byte offset of the unit's first byte (input and output)
+    uint32_t nbytes;  // bytes in the unit
+    uint32_t meta;    // bits 0..23 schedule index, bits 24..25 op, bits 26..31 flags
+    uint32_t w[4];    // CTR: nonce words 0,1 then the 64-bit counter of the unit's
+                      //      first block as an integer (w[2] low half, w[3] high half)
+                      // CBC: the 16 bytes that precede the unit's first block in
+                      //      the chain (the IV for a request's first unit)
+};
+static_assert(sizeof(Unit) == 32, "Unit is 32 bytes");
+
+constexpr uint32_t META_KEY_MASK = 0x00FFFFFFu;
+constexpr uint32_t META_OP_SHIFT = 24;
+constexpr uint32_t FLAG_PRED_IN = 1u << 26;  // CBC-dec: predecessor is in[off-16 .. off)
+constexpr uint32_t MAX_KEYS = 1u << 24;
+
+// Table image in device memory (2304 words), written once per context:
+//   [0, 1024)     Te0..Te3, 256 words each (encryption round tables)
+//   [1024, 2048)  Td0..Td3 (equivalent inverse cipher round tables)
+//   [2048, 2304)  Si4: the inverse S-box byte repeated in all four bytes
+constexpr int TIMG_WORDS = 2304;
+
+// Launch shape of the parallel-mode (tile) kernel.
+struct TileLaunch {
+    int nb = 2;             // 16-byte blocks per lane per step (1, 2 or 4)
+    int wg_threads = 1024;  // threads per workgroup (multiple of 64, <= 1024)
+    int grid = 0;           // workgroups; 0 = one per compute unit
+};
+bool tile_shape_supported(int nb, int wg_threads);
+
+struct ChainLaunch {
+    int wg_threads = 64;
+    int grid = 0;  // 0 = as many as the chains need
+};
+
+// Host-side launchers (aes_kernels.hip).  Each returns a hipError_t value.
+int launch_ctr_tiles(const Unit *d_units, uint32_t n_units, const aes_schedule_t *d_sched,
+                     uint32_t n_sched, const uint32_t *d_timg, const uint8_t *d_in,
+                     uint8_t *d_out, const TileLaunch &cfg, int n_cu, void *stream);
+// d_preds: NULL, or one 16-byte predecessor per unit written by
+// launch_snapshot_preds (used for FLAG_PRED_IN units instead of reading d_in).
+int launch_cbcdec_tiles(const Unit *d_units, uint32_t n_units, const aes_schedule_t *d_sched,
+                        uint32_t n_sched, const uint32_t *d_timg, const void *d_preds,
+                        const uint8_t *d_in, uint8_t *d_out, const TileLaunch &cfg, int n_cu,
+                        void *stream);
+int launch_cbcenc_chains(const Unit *d_units, uint32_t n_units, const aes_schedule_t *d_sched,
+                         uint32_t n_sched, const uint32_t *d_timg, const uint8_t *d_in,
+                         uint8_t *d_out, const ChainLaunch &cfg, int n_cu, void *stream);
+// In-place CBC decryption: copies in[off-16, off) of every FLAG_PRED_IN unit u
+// to d_preds[16u..16u+15] before the tile kernel overwrites those bytes.
+int launch_snapshot_preds(const Unit *d_units, uint32_t n_units, const uint8_t *d_in,
+                          void *d_preds, void *stream);
+
+// Host table generation (tables.cpp).
+void make_table_image(uint32_t img[TIMG_WORDS]);
+int expand_key(const uint8_t *key, uint32_t key_bits, aes_schedule_t *out);
+
+}  // namespace aesgpu

@@ -1,0 +1,246 @@
+"""Host-side tests of the C ABI (no GPU): exports, key expansion, validation
+errors and the work-unit planner, run on a host-only (AES_DEVICE_NONE) context."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import gen, workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def ag():
+    from paper_1305_3345_amd import aesgpu
+    if not os.path.exists(aesgpu.LIB_PATH):
+        from paper_1305_3345_amd import build
+        build.build()
+    aesgpu.lib()
+    return aesgpu
+
+
+@pytest.fixture()
+def hctx(ag):
+    c = ag.Context(ag.AES_DEVICE_NONE)
+    yield c
+    c.close()
+
+
+def declared_functions():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if fn.endswith(".h"):
+            text = open(os.path.join(inc, fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(aes_[a-z0-9_]+)\s*\(", text))
+    return names
+
+
+def test_library_exports_every_declared_symbol(ag):
+    import ctypes
+    names = declared_functions()
+    assert {"aes_expand_key", "aes_cbc_encrypt_batch", "aes_cbc_decrypt_batch",
+            "aes_ctr_batch", "aes_batch"} <= names
+    L = ctypes.CDLL(ag.LIB_PATH)
+    missing = [n for n in sorted(names) if not hasattr(L, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("bits", (128, 192, 256))
+def test_expand_key_matches_oracle(ag, bits):
+    r = np.random.default_rng(bits)
+    for _ in range(5):
+        key = r.integers(0, 256, bits // 8, dtype=np.uint8)
+        s = ag.expand_key(key, bits)
+        nr = {128: 10, 192: 12, 256: 14}[bits]
+        assert s["key_bits"] == bits and s["nr"] == nr
+        w = oracle.expand_key(key, bits)  # (4(nr+1), 4) bytes
+        ek = s["ek"][: 4 * (nr + 1)].astype("<u4").view(np.uint8).reshape(-1, 4)
+        assert np.array_equal(ek, w)
+        assert not s["ek"][4 * (nr + 1):].any() and not s["dk"][4 * (nr + 1):].any()
+        # equivalent inverse cipher: first and last round keys are swapped, unchanged
+        assert np.array_equal(s["dk"][:4], s["ek"][4 * nr: 4 * nr + 4])
+        assert np.array_equal(s["dk"][4 * nr: 4 * nr + 4], s["ek"][:4])
+
+
+def test_expand_key_rejects_bad_sizes(ag):
+    with pytest.raises(ag.AesError) as e:
+        ag.expand_key(bytes(16), 100)
+    assert e.value.status == ag.AES_ERR_KEYSIZE
+
+
+def _reqs(n=4, op=2, length=4096):
+    r = np.zeros(n, workloads.REQ_DTYPE)
+    r["offset"] = np.arange(n) * length
+    r["length"] = length
+    r["op"] = op
+    return r
+
+
+FAKE = 1 << 40  # host-only context: device pointers are never dereferenced
+
+
+@pytest.mark.parametrize("case,status", [
+    ("cbc_len", "AES_ERR_LENGTH"),
+    ("unaligned", "AES_ERR_RANGE"),
+    ("past_end", "AES_ERR_RANGE"),
+    ("key_idx", "AES_ERR_RANGE"),
+    ("overlap", "AES_ERR_OVERLAP"),
+    ("overlap_unsorted", "AES_ERR_OVERLAP"),
+    ("bad_op", "AES_ERR_ARG"),
+    ("huge", "AES_ERR_LENGTH"),
+    ("alias", "AES_ERR_OVERLAP"),
+    ("null", "AES_ERR_ARG"),
+    ("ok", "AES_ERR_DEVICE"),
+])
+def test_validation_errors(ag, hctx, case, status):
+    reqs = _reqs(op=1)
+    d_in, d_out, buf = FAKE, FAKE + (1 << 30), 4 * 4096
+    if case == "cbc_len":
+        reqs["length"][2] = 4008
+    elif case == "unaligned":
+        reqs["offset"][1] += 8
+    elif case == "past_end":
+        reqs["length"][3] = 8192
+    elif case == "key_idx":
+        reqs["key_idx"][0] = 1
+    elif case == "overlap":
+        reqs["offset"][2] = 4096 + 16
+        reqs["length"][2] = 1024
+    elif case == "overlap_unsorted":
+        reqs = reqs[[3, 0, 2, 1]].copy()
+        reqs["offset"][0] = 4096 * 2 + 4096 - 16
+        reqs["length"][0] = 32
+        reqs["offset"][2] = 0
+    elif case == "bad_op":
+        reqs["op"][1] = 3
+    elif case == "huge":
+        reqs["length"][0] = 1 << 32
+    elif case == "alias":
+        d_out = d_in + 16
+    elif case == "null":
+        d_in = 0
+    with pytest.raises(ag.AesError) as e:
+        ag.batch(hctx, FAKE + (2 << 30), d_in, d_out, reqs, buf_bytes=buf, n_scheds=1)
+    assert e.value.status == getattr(ag, status)
+
+
+def test_empty_and_zero_length_are_noops(ag, hctx):
+    ag.batch(hctx, 0, 0, 0, np.zeros(0, workloads.REQ_DTYPE), buf_bytes=0, n_scheds=0)
+    reqs = _reqs()
+    reqs["length"] = 0
+    ag.batch(hctx, FAKE, FAKE, FAKE + (1 << 30), reqs, buf_bytes=4 * 4096, n_scheds=1)
+
+
+def test_single_mode_entry_points_validate(ag, hctx):
+    n = 3
+    off = np.arange(n, dtype=np.uint64) * 4096
+    ln = np.full(n, 4096, np.uint64)
+    ki = np.zeros(n, np.uint32)
+    iv = np.zeros((n, 16), np.uint8)
+    for fn in (ag.cbc_encrypt_batch, ag.cbc_decrypt_batch, ag.ctr_batch):
+        with pytest.raises(ag.AesError) as e:
+            fn(hctx, FAKE, FAKE, FAKE + (1 << 30), off, ln, ki, iv, buf_bytes=n * 4096,
+               n_scheds=1)
+        assert e.value.status == ag.AES_ERR_DEVICE  # valid, but no device
+    ln[1] = 17
+    with pytest.raises(ag.AesError) as e:
+        ag.cbc_decrypt_batch(hctx, FAKE, FAKE, FAKE + (1 << 30), off, ln, ki, iv,
+                             buf_bytes=n * 4096, n_scheds=1)
+    assert e.value.status == ag.AES_ERR_LENGTH
+    ag.ctr_batch  # CTR takes any length: only the device is missing
+    with pytest.raises(ag.AesError) as e:
+        ag.ctr_batch(hctx, FAKE, FAKE, FAKE + (1 << 30), off, ln, ki, iv, buf_bytes=n * 4096,
+                     n_scheds=1)
+    assert e.value.status == ag.AES_ERR_DEVICE
+
+
+# ------------------------------------------------------------------- planner
+
+def _check_plan(ag, plan, reqs, tile):
+    units = plan.units()
+    info = plan.info()
+    assert info["payload_bytes"] == int(reqs["length"].sum())
+    op_of = (units["meta"] >> 24) & 3
+    covered = {}
+    for u in units:
+        covered.setdefault(int(u["offset"]), []).append(u)
+    # every request's bytes are covered exactly once by units of its op and key
+    total = 0
+    for r in reqs:
+        off, ln, op = int(r["offset"]), int(r["length"]), int(r["op"])
+        if ln == 0:
+            continue
+        pos = 0
+        while pos < ln:
+            us = covered.get(off + pos)
+            assert us and len(us) == 1, (off, pos)
+            u = us[0]
+            assert ((int(u["meta"]) >> 24) & 3) == op
+            assert (int(u["meta"]) & 0xFFFFFF) == int(r["key_idx"])
+            n = int(u["nbytes"])
+            if op == ag.AES_OP_CBC_ENC:
+                assert n == ln and pos == 0
+                assert np.array_equal(u["w"].astype("<u4").view(np.uint8), r["iv"])
+            else:
+                assert n == min(tile, ln - pos)
+                if op == ag.AES_OP_CTR:
+                    assert np.array_equal(u["w"][:2].astype("<u4").view(np.uint8), r["iv"][:8])
+                    low = int.from_bytes(r["iv"][8:].tobytes(), "big")
+                    ctr = int(u["w"][2]) | (int(u["w"][3]) << 32)
+                    assert ctr == (low + pos // 16) % (1 << 64)
+                else:
+                    pred_in = bool(int(u["meta"]) & (1 << 26))
+                    assert pred_in == (pos > 0)
+                    if pos == 0:
+                        assert np.array_equal(u["w"].astype("<u4").view(np.uint8), r["iv"])
+            pos += n
+            total += n
+    assert total == info["payload_bytes"]
+    assert len(units) == info["n_units_cbc_dec"] + info["n_units_ctr"] + info["n_chains_cbc_enc"]
+    # order: CBC-dec tiles, CTR tiles, then chains longest first
+    k = info["n_units_cbc_dec"]
+    assert (op_of[:k] == ag.AES_OP_CBC_DEC).all()
+    assert (op_of[k:k + info["n_units_ctr"]] == ag.AES_OP_CTR).all()
+    ch = units[k + info["n_units_ctr"]:]
+    assert (np.diff(ch["nbytes"].astype(np.int64)) <= 0).all()
+
+
+def test_plan_covers_config3_batch(ag, hctx):
+    wl = workloads.config3(n_reqs=600, max_pages=64)
+    plan = ag.Plan(hctx, wl.reqs, wl.keys.shape[0], wl.buf_bytes)
+    _check_plan(ag, plan, wl.reqs, 4096)
+    info = plan.info()
+    assert info["extent_bytes"] == wl.buf_bytes and info["tile_bytes"] == 4096
+    with pytest.raises(ag.AesError) as e:
+        plan.launch(FAKE, FAKE, FAKE + (1 << 40))
+    assert e.value.status == ag.AES_ERR_DEVICE
+    plan.close()
+
+
+def test_plan_ragged_ctr_and_counter_wrap(ag, hctx):
+    r = np.zeros(5, workloads.REQ_DTYPE)
+    lens = [1, 4095, 4097, 3 * 4096 + 5, 16 * 1000]
+    off = 0
+    for i, ln in enumerate(lens):
+        r["offset"][i] = off
+        r["length"][i] = ln
+        off += (ln + 15) // 16 * 16 + 32
+    r["op"] = ag.AES_OP_CTR
+    r["iv"] = gen.bytes_(0, 2, 80).reshape(5, 16)
+    r["iv"][3, 8:] = np.frombuffer(((1 << 64) - 3).to_bytes(8, "big"), np.uint8)
+    plan = ag.Plan(hctx, r, 1, off)
+    _check_plan(ag, plan, r, 4096)
+    plan.close()
+
+
+def test_plan_unsorted_requests(ag, hctx):
+    wl = workloads.config3(n_reqs=50, max_pages=8)
+    perm = np.random.default_rng(1).permutation(50)
+    plan = ag.Plan(hctx, wl.reqs[perm], wl.keys.shape[0], wl.buf_bytes)
+    _check_plan(ag, plan, wl.reqs[perm], 4096)
+    plan.close()
