@@ -38,6 +38,11 @@ def parse():
                     help="pages per run timed on the CPU oracle")
     ap.add_argument("--per-call-iters", type=int, default=3,
                     help="iterations of the host-metadata single-call form (0 = skip)")
+    ap.add_argument("--runs", default="cbc_dec_128,ctr_128,cbc_dec_256,ctr_256",
+                    help="comma-separated subset of the step's runs (for profiling)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also copy the 256 MiB input once device-to-device (a kernel of "
+                         "known traffic for scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -95,12 +100,15 @@ def main():
     runs = []  # (name, kernel, plan, d_scheds, payload, units)
     for bits in (128, 256):
         for op, kname in ((workloads.OP_CBC_DEC, "cbcdec_tiles"), (workloads.OP_CTR, "ctr_tiles")):
+            name = f"{workloads.OP_NAMES[op]}_{bits}"
+            if name not in args.runs.split(","):
+                continue
             wl = workloads.config2(op, bits, n_pages=n_pages)
             d_s = aesgpu.schedules_to_device(aesgpu.expand_keys(wl.keys, wl.key_bits), dev)
             plan = aesgpu.Plan(ctx, wl.reqs, wl.keys.shape[0], nbytes)
             info = plan.info()
             units = info["n_units_cbc_dec"] + info["n_units_ctr"]
-            runs.append((f"{workloads.OP_NAMES[op]}_{bits}", kname, plan, d_s,
+            runs.append((name, kname, plan, d_s,
                          info["payload_bytes"], units, wl))
     stream = torch.cuda.current_stream()
 
@@ -112,6 +120,9 @@ def main():
             if events is not None:
                 events[i][1].record(stream)
 
+    if args.calib_copy:
+        d_out.copy_(d_in)
+        torch.cuda.synchronize()
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
