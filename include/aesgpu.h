@@ -210,6 +210,64 @@ int aes_plan_units(const aes_plan_t *plan, aes_unit_t *out, uint64_t max, uint64
 /* Waits for the device to be idle, then frees the plan.  NULL is a no-op. */
 void aes_plan_destroy(aes_plan_t *plan);
 
+/* ------------------------------------------------------- launch configuration */
+
+/* Kernel shapes of a context; read at every launch (tile_bytes when a plan is
+ * created).  Defaults: tile 4096, CTR and CBC-decrypt tiles 2 blocks per lane
+ * x 1024 threads, chains 64 lanes per wave x 256 threads, fused kernel 2
+ * blocks per lane, fuse = 1, grid = 0 (one workgroup per compute unit). */
+typedef struct aes_launch_config {
+    uint32_t tile_bytes;  /* bytes per CTR / CBC-decrypt unit: multiple of 1024 */
+    uint32_t ctr_nb;      /* CTR tile kernel: 16-byte blocks per lane per step (1, 2, 4) */
+    uint32_t ctr_wg;      /* CTR tile kernel: threads per workgroup (256, 512, 1024) */
+    uint32_t dec_nb;      /* CBC-decrypt tile kernel: as ctr_nb */
+    uint32_t dec_wg;      /* CBC-decrypt tile kernel: as ctr_wg */
+    uint32_t chain_lanes; /* CBC-encrypt: chains (active lanes) per wave, 1..64 */
+    uint32_t chain_wg;    /* CBC-encrypt chain kernel: threads per workgroup */
+    uint32_t mixed_nb;    /* fused mixed-batch kernel: blocks per lane (1, 2) */
+    uint32_t fuse;        /* 1: a batch mixing ops runs as one launch; 0: one launch per op */
+    uint32_t grid;        /* workgroups of tile and fused kernels; 0 = one per compute unit */
+    uint32_t reserved[6];
+} aes_launch_config_t;
+
+int aes_ctx_get_config(const aes_ctx_t *ctx, aes_launch_config_t *cfg);
+/* Errors: AES_ERR_ARG for an unsupported shape (nothing changes). */
+int aes_ctx_set_config(aes_ctx_t *ctx, const aes_launch_config_t *cfg);
+
+/* Autotuner: times plan launches of reqs on the caller's buffers (d_in must
+ * differ from d_out; d_out is overwritten with the batch's result) for tile
+ * sizes, tile-kernel shapes, chain lanes and the fusion switch by coordinate
+ * descent (median of iters launches each), leaves the fastest configuration
+ * set in ctx and copies it to *best (may be NULL).  Plans created afterwards
+ * use its tile size.  Errors: as aes_batch; AES_ERR_OVERLAP if d_in == d_out. */
+int aes_tune(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_scheds,
+             uint64_t buf_bytes, const aes_schedule_t *d_scheds, const uint8_t *d_in,
+             uint8_t *d_out, uint32_t iters, aes_launch_config_t *best);
+
+/* ------------------------------------------------ per-request launches, graphs */
+
+/* One request, one kernel launch, with the request passed by value (no unit
+ * table, no copy): the plain per-call form that batching is compared with
+ * (paper section 3.1: every GPU call pays a launch).  Same checks as
+ * aes_batch for one request. */
+int aes_request_launch(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+                       const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
+                       const aes_req_t *req, void *stream);
+
+/* An instantiated HIP graph owned by the library. */
+typedef struct aes_graph aes_graph_t;
+
+/* Captures one launch of a plan (with these buffers) into a graph. */
+int aes_plan_graph(aes_plan_t *plan, const aes_schedule_t *d_scheds, const uint8_t *d_in,
+                   uint8_t *d_out, aes_graph_t **out);
+/* Captures n_reqs per-request launches (aes_request_launch) into one graph. */
+int aes_requests_graph(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+                       const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
+                       const aes_req_t *reqs, uint64_t n_reqs, aes_graph_t **out);
+/* Launches a graph on stream.  Errors: AES_ERR_ARG, AES_ERR_DEVICE. */
+int aes_graph_launch(aes_graph_t *graph, void *stream);
+void aes_graph_destroy(aes_graph_t *graph);
+
 #ifdef __cplusplus
 }
 #endif

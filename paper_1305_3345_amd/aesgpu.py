@@ -49,6 +49,10 @@ PLAN_INFO_DTYPE = np.dtype([("n_units_cbc_dec", "<u8"), ("n_units_ctr", "<u8"),
                             ("n_chains_cbc_enc", "<u8"), ("payload_bytes", "<u8"),
                             ("extent_bytes", "<u8"), ("tile_bytes", "<u4"),
                             ("reserved", "<u4")])
+CONFIG_DTYPE = np.dtype([(k, "<u4") for k in (
+    "tile_bytes", "ctr_nb", "ctr_wg", "dec_nb", "dec_wg", "chain_lanes", "chain_wg", "mixed_nb",
+    "fuse", "grid")] + [("reserved", "<u4", (6,))])
+assert CONFIG_DTYPE.itemsize == 64
 assert SCHED_DTYPE.itemsize == 512 and REQ_DTYPE.itemsize == 40 and UNIT_DTYPE.itemsize == 32
 
 _lib = None
@@ -91,6 +95,14 @@ def lib():
             "aes_plan_info": (i32, [p, p]),
             "aes_plan_units": (i32, [p, p, u64, ctypes.POINTER(u64)]),
             "aes_plan_destroy": (None, [p]),
+            "aes_ctx_get_config": (i32, [p, p]),
+            "aes_ctx_set_config": (i32, [p, p]),
+            "aes_tune": (i32, [p, p, u64, u32, u64, p, p, p, u32, p]),
+            "aes_request_launch": (i32, [p, p, u32, p, p, u64, p, p]),
+            "aes_plan_graph": (i32, [p, p, p, p, ctypes.POINTER(p)]),
+            "aes_requests_graph": (i32, [p, p, u32, p, p, u64, p, u64, ctypes.POINTER(p)]),
+            "aes_graph_launch": (i32, [p, p]),
+            "aes_graph_destroy": (None, [p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -172,6 +184,21 @@ class Context:
         _check(lib().aes_ctx_create(device, ctypes.byref(h)), "aes_ctx_create")
         self.handle = h.value
         self.device = device
+
+    def get_config(self) -> dict:
+        """aes_ctx_get_config as a dict."""
+        c = np.zeros(1, CONFIG_DTYPE)
+        _check(lib().aes_ctx_get_config(self.handle, c.ctypes.data), "aes_ctx_get_config")
+        return {k: int(c[0][k]) for k in CONFIG_DTYPE.names if k != "reserved"}
+
+    def set_config(self, **kw):
+        """aes_ctx_set_config with the given fields changed."""
+        cur = self.get_config()
+        cur.update(kw)
+        c = np.zeros(1, CONFIG_DTYPE)
+        for k, v in cur.items():
+            c[0][k] = v
+        _check(lib().aes_ctx_set_config(self.handle, c.ctypes.data), "aes_ctx_set_config")
 
     def close(self):
         if self.handle:
@@ -273,6 +300,69 @@ class Plan:
     def close(self):
         if self.handle:
             lib().aes_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tune(ctx: Context, reqs: np.ndarray, d_scheds, d_in, d_out, iters: int = 5,
+         buf_bytes: int | None = None, n_scheds: int | None = None) -> dict:
+    """aes_tune: sets and returns the fastest launch configuration for reqs."""
+    reqs = np.ascontiguousarray(reqs, dtype=REQ_DTYPE)
+    best = np.zeros(1, CONFIG_DTYPE)
+    bb = _nbytes(d_in) if buf_bytes is None else buf_bytes
+    _check(lib().aes_tune(ctx.handle, reqs.ctypes.data, reqs.size,
+                          _sched_count(d_scheds, n_scheds), bb, _ptr(d_scheds), _ptr(d_in),
+                          _ptr(d_out), iters, best.ctypes.data), "aes_tune")
+    return {k: int(best[0][k]) for k in CONFIG_DTYPE.names if k != "reserved"}
+
+
+def request_launch(ctx: Context, d_scheds, d_in, d_out, req, buf_bytes: int | None = None,
+                   n_scheds: int | None = None, stream=None):
+    """aes_request_launch for one REQ_DTYPE record."""
+    r = np.ascontiguousarray(np.asarray(req, dtype=REQ_DTYPE).reshape(1))
+    bb = _nbytes(d_in) if buf_bytes is None else buf_bytes
+    _check(lib().aes_request_launch(ctx.handle, _ptr(d_scheds), _sched_count(d_scheds, n_scheds),
+                                    _ptr(d_in), _ptr(d_out), bb, r.ctypes.data, _stream(stream)),
+           "aes_request_launch")
+
+
+class Graph:
+    """An instantiated HIP graph: aes_plan_graph / aes_requests_graph, launch, destroy."""
+
+    def __init__(self, handle, keep=()):
+        self.handle = handle
+        self._keep = keep
+
+    @classmethod
+    def of_plan(cls, plan: Plan, d_scheds, d_in, d_out):
+        h = ctypes.c_void_p()
+        _check(lib().aes_plan_graph(plan.handle, _ptr(d_scheds), _ptr(d_in), _ptr(d_out),
+                                    ctypes.byref(h)), "aes_plan_graph")
+        return cls(h.value, (plan,))
+
+    @classmethod
+    def of_requests(cls, ctx: Context, d_scheds, d_in, d_out, reqs: np.ndarray,
+                    buf_bytes: int | None = None, n_scheds: int | None = None):
+        reqs = np.ascontiguousarray(reqs, dtype=REQ_DTYPE)
+        h = ctypes.c_void_p()
+        bb = _nbytes(d_in) if buf_bytes is None else buf_bytes
+        _check(lib().aes_requests_graph(ctx.handle, _ptr(d_scheds),
+                                        _sched_count(d_scheds, n_scheds), _ptr(d_in),
+                                        _ptr(d_out), bb, reqs.ctypes.data, reqs.size,
+                                        ctypes.byref(h)), "aes_requests_graph")
+        return cls(h.value, (ctx,))
+
+    def launch(self, stream=None):
+        _check(lib().aes_graph_launch(self.handle, _stream(stream)), "aes_graph_launch")
+
+    def close(self):
+        if self.handle:
+            lib().aes_graph_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -128,6 +128,7 @@ struct Planned {
     std::vector<Unit> chains;  // CBC-encrypt chains, longest first
     uint64_t payload = 0;
     uint64_t extent = 0;
+    uint64_t dec_bytes = 0, ctr_bytes = 0, chain_bytes = 0;
     bool dec_has_pred_in = false;
 };
 
@@ -156,6 +157,8 @@ int plan_units(const aes_req_t *reqs, uint64_t n, uint32_t tile_bytes, Planned &
                 continue;
             p.payload += r.length;
             p.extent = std::max(p.extent, r.offset + r.length);
+            (r.op == AES_OP_CBC_ENC ? p.chain_bytes
+                                    : r.op == AES_OP_CTR ? p.ctr_bytes : p.dec_bytes) += r.length;
             const uint32_t meta_base = r.key_idx | (r.op << META_OP_SHIFT);
             if (r.op == AES_OP_CBC_ENC) {
                 Unit u;
@@ -226,6 +229,17 @@ struct aes_ctx {
     uint32_t tile_bytes = DEFAULT_TILE;
     TileLaunch tile_ctr, tile_dec;
     ChainLaunch chain;
+    int mixed_nb = 2;
+    bool fuse = true;        // one launch for batches that mix ops
+    int grid = 0;            // tile / fused kernel workgroups, 0 = one per compute unit
+    hipStream_t capture = nullptr;  // private stream for graph capture and tuning
+};
+
+struct aes_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int device = 0;
+    uint64_t n_nodes = 0;
 };
 
 struct aes_plan {
@@ -235,6 +249,7 @@ struct aes_plan {
     uint64_t buf_bytes = 0;
     void *d_units = nullptr;  // [dec | ctr | chains] units, then dec predecessor snapshots
     size_t n_dec = 0, n_ctr = 0, n_chain = 0;
+    uint32_t tile_bytes = DEFAULT_TILE;
 };
 
 namespace {
@@ -243,28 +258,77 @@ size_t units_bytes(size_t n_dec, size_t n_ctr, size_t n_chain) {
     return (n_dec + n_ctr + n_chain) * sizeof(Unit) + n_dec * 16;
 }
 
-// Launches the kernels of one planned batch whose unit table is at d_units.
-int launch_planned(aes_ctx *ctx, void *d_units, size_t n_dec, size_t n_ctr, size_t n_chain,
-                   bool pred_in, const aes_schedule_t *d_scheds, uint32_t n_scheds,
-                   const uint8_t *d_in, uint8_t *d_out, void *stream) {
-    Unit *u = (Unit *)d_units;
+struct PlanView {
+    void *d_units;
+    size_t n_dec, n_ctr, n_chain;
+    bool pred_in;
+    uint64_t dec_bytes, ctr_bytes;
+};
+
+PlanView view_of(const Planned &p, void *d_units) {
+    return PlanView{d_units, p.dec.size(), p.ctr.size(), p.chains.size(), p.dec_has_pred_in,
+                    p.dec_bytes, p.ctr_bytes};
+}
+
+// Workgroups of the fused kernel that hold the decryption tables: a share of
+// the grid proportional to the CBC-decrypt bytes among the parallel bytes.
+uint32_t dec_workgroups(const PlanView &v, int grid) {
+    if (!v.n_dec)
+        return 0;
+    if (!v.n_ctr && !v.n_chain)
+        return (uint32_t)grid;
+    const double share = (double)v.dec_bytes / (double)(v.dec_bytes + v.ctr_bytes + 1);
+    long k = std::lround(share * grid);
+    if (k < 1)
+        k = 1;
+    if (k > grid - 1)
+        k = grid - 1;
+    return (uint32_t)k;
+}
+
+// Launches the kernels of one planned batch whose unit table is at v.d_units.
+int launch_planned(aes_ctx *ctx, const PlanView &v, const aes_schedule_t *d_scheds,
+                   uint32_t n_scheds, const uint8_t *d_in, uint8_t *d_out, void *stream) {
+    Unit *u = (Unit *)v.d_units;
     Unit *u_dec = u;
-    Unit *u_ctr = u + n_dec;
-    Unit *u_chain = u + n_dec + n_ctr;
+    Unit *u_ctr = u + v.n_dec;
+    Unit *u_chain = u + v.n_dec + v.n_ctr;
     void *d_preds = nullptr;
     int e;
-    if (n_dec && pred_in && d_in == d_out) {
-        d_preds = (void *)(u + n_dec + n_ctr + n_chain);
-        if ((e = launch_snapshot_preds(u_dec, (uint32_t)n_dec, d_in, d_preds, stream)))
+    if (v.n_dec && v.pred_in && d_in == d_out) {
+        d_preds = (void *)(u + v.n_dec + v.n_ctr + v.n_chain);
+        if ((e = launch_snapshot_preds(u_dec, (uint32_t)v.n_dec, d_in, d_preds, stream)))
             return hip_fail((hipError_t)e);
     }
-    if ((e = launch_cbcdec_tiles(u_dec, (uint32_t)n_dec, d_scheds, n_scheds, ctx->d_timg, d_preds,
-                                 d_in, d_out, ctx->tile_dec, ctx->n_cu, stream)))
+    const int kinds = (v.n_dec > 0) + (v.n_ctr > 0) + (v.n_chain > 0);
+    if (ctx->fuse && kinds > 1) {
+        const int grid = ctx->grid > 0 ? ctx->grid : ctx->n_cu;
+        MixedArgs a;
+        a.dec = u_dec;
+        a.ctr = u_ctr;
+        a.chains = u_chain;
+        a.preds = (const uint32_t *)d_preds;
+        a.sched = d_scheds;
+        a.timg = ctx->d_timg;
+        a.in = d_in;
+        a.out = d_out;
+        a.n_dec = (uint32_t)v.n_dec;
+        a.n_ctr = (uint32_t)v.n_ctr;
+        a.n_chain = (uint32_t)v.n_chain;
+        a.n_sched = n_scheds;
+        a.n_dec_wg = dec_workgroups(v, grid);
+        a.chain_lanes = (uint32_t)ctx->chain.lanes;
+        if ((e = launch_mixed(a, ctx->mixed_nb, grid, stream)))
+            return hip_fail((hipError_t)e);
+        return AES_OK;
+    }
+    if ((e = launch_cbcdec_tiles(u_dec, (uint32_t)v.n_dec, d_scheds, n_scheds, ctx->d_timg,
+                                 d_preds, d_in, d_out, ctx->tile_dec, ctx->n_cu, stream)))
         return hip_fail((hipError_t)e);
-    if ((e = launch_ctr_tiles(u_ctr, (uint32_t)n_ctr, d_scheds, n_scheds, ctx->d_timg, d_in, d_out,
-                              ctx->tile_ctr, ctx->n_cu, stream)))
+    if ((e = launch_ctr_tiles(u_ctr, (uint32_t)v.n_ctr, d_scheds, n_scheds, ctx->d_timg, d_in,
+                              d_out, ctx->tile_ctr, ctx->n_cu, stream)))
         return hip_fail((hipError_t)e);
-    if ((e = launch_cbcenc_chains(u_chain, (uint32_t)n_chain, d_scheds, n_scheds, ctx->d_timg,
+    if ((e = launch_cbcenc_chains(u_chain, (uint32_t)v.n_chain, d_scheds, n_scheds, ctx->d_timg,
                                   d_in, d_out, ctx->chain, ctx->n_cu, stream)))
         return hip_fail((hipError_t)e);
     return AES_OK;
@@ -329,8 +393,7 @@ int run_batch(aes_ctx *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
     pack_units(p, s.h_stage);
     HIP_TRY(hipMemcpyAsync(s.d_units, s.h_stage, ubytes, hipMemcpyHostToDevice,
                            (hipStream_t)stream));
-    st = launch_planned(ctx, s.d_units, p.dec.size(), p.ctr.size(), p.chains.size(),
-                        p.dec_has_pred_in, d_scheds, n_scheds, d_in, d_out, stream);
+    st = launch_planned(ctx, view_of(p, s.d_units), d_scheds, n_scheds, d_in, d_out, stream);
     if (st)
         return st;
     HIP_TRY(hipEventRecord(s.ev, (hipStream_t)stream));
@@ -455,6 +518,8 @@ void aes_ctx_destroy(aes_ctx_t *ctx) {
         }
         if (ctx->d_timg)
             (void)hipFree(ctx->d_timg);
+        if (ctx->capture)
+            (void)hipStreamDestroy(ctx->capture);
     }
     delete ctx;
 }
@@ -503,6 +568,7 @@ int aes_plan_create(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n, uint32_t 
     if (!pl)
         return AES_ERR_NOMEM;
     pl->ctx = ctx;
+    pl->tile_bytes = ctx->tile_bytes;
     pl->n_scheds = n_scheds;
     pl->buf_bytes = buf_bytes;
     if ((st = plan_units(reqs, n, ctx->tile_bytes, pl->p))) {
@@ -557,8 +623,8 @@ int aes_plan_launch(aes_plan_t *plan, const aes_schedule_t *d_scheds, const uint
     if (ctx->device == AES_DEVICE_NONE)
         return AES_ERR_DEVICE;
     HIP_TRY(hipSetDevice(ctx->device));
-    return launch_planned(ctx, plan->d_units, plan->n_dec, plan->n_ctr, plan->n_chain,
-                          plan->p.dec_has_pred_in, d_scheds, plan->n_scheds, d_in, d_out, stream);
+    return launch_planned(ctx, view_of(plan->p, plan->d_units), d_scheds, plan->n_scheds, d_in,
+                          d_out, stream);
 }
 
 int aes_plan_info(const aes_plan_t *plan, aes_plan_info_t *info) {
@@ -570,7 +636,7 @@ int aes_plan_info(const aes_plan_t *plan, aes_plan_info_t *info) {
     info->n_chains_cbc_enc = plan->n_chain;
     info->payload_bytes = plan->p.payload;
     info->extent_bytes = plan->p.extent;
-    info->tile_bytes = plan->ctx->tile_bytes;
+    info->tile_bytes = plan->tile_bytes;
     return AES_OK;
 }
 
@@ -599,6 +665,325 @@ void aes_plan_destroy(aes_plan_t *plan) {
         (void)hipFree(plan->d_units);
     }
     delete plan;
+}
+
+// ----------------------------------------------------------- launch config
+
+int aes_ctx_get_config(const aes_ctx_t *ctx, aes_launch_config_t *cfg) {
+    if (!ctx || !cfg)
+        return AES_ERR_ARG;
+    memset(cfg, 0, sizeof(*cfg));
+    cfg->tile_bytes = ctx->tile_bytes;
+    cfg->ctr_nb = (uint32_t)ctx->tile_ctr.nb;
+    cfg->ctr_wg = (uint32_t)ctx->tile_ctr.wg_threads;
+    cfg->dec_nb = (uint32_t)ctx->tile_dec.nb;
+    cfg->dec_wg = (uint32_t)ctx->tile_dec.wg_threads;
+    cfg->chain_lanes = (uint32_t)ctx->chain.lanes;
+    cfg->chain_wg = (uint32_t)ctx->chain.wg_threads;
+    cfg->mixed_nb = (uint32_t)ctx->mixed_nb;
+    cfg->fuse = ctx->fuse ? 1u : 0u;
+    cfg->grid = (uint32_t)ctx->grid;
+    return AES_OK;
+}
+
+int aes_ctx_set_config(aes_ctx_t *ctx, const aes_launch_config_t *cfg) {
+    if (!ctx || !cfg)
+        return AES_ERR_ARG;
+    if (cfg->tile_bytes < 1024 || cfg->tile_bytes > (1u << 24) || (cfg->tile_bytes & 1023))
+        return AES_ERR_ARG;
+    if (!tile_shape_supported((int)cfg->ctr_nb, (int)cfg->ctr_wg) ||
+        !tile_shape_supported((int)cfg->dec_nb, (int)cfg->dec_wg))
+        return AES_ERR_ARG;
+    if (cfg->chain_lanes < 1 || cfg->chain_lanes > 64 || cfg->chain_wg < 64 ||
+        cfg->chain_wg > 1024 || (cfg->chain_wg & 63))
+        return AES_ERR_ARG;
+    if (cfg->mixed_nb != 1 && cfg->mixed_nb != 2)
+        return AES_ERR_ARG;
+    if (cfg->fuse > 1 || cfg->grid > 65535)
+        return AES_ERR_ARG;
+    ctx->tile_bytes = cfg->tile_bytes;
+    ctx->tile_ctr.nb = (int)cfg->ctr_nb;
+    ctx->tile_ctr.wg_threads = (int)cfg->ctr_wg;
+    ctx->tile_ctr.grid = (int)cfg->grid;
+    ctx->tile_dec.nb = (int)cfg->dec_nb;
+    ctx->tile_dec.wg_threads = (int)cfg->dec_wg;
+    ctx->tile_dec.grid = (int)cfg->grid;
+    ctx->chain.lanes = (int)cfg->chain_lanes;
+    ctx->chain.wg_threads = (int)cfg->chain_wg;
+    ctx->mixed_nb = (int)cfg->mixed_nb;
+    ctx->fuse = cfg->fuse != 0;
+    ctx->grid = (int)cfg->grid;
+    return AES_OK;
+}
+
+// ---------------------------------------------------- one request, one launch
+
+int aes_request_launch(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+                       const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
+                       const aes_req_t *req, void *stream) {
+    if (!ctx || !req)
+        return AES_ERR_ARG;
+    int st = check_buffers(d_in, d_out, buf_bytes, 1, d_scheds);
+    if (st)
+        return st;
+    if ((st = validate(req, 1, n_scheds, buf_bytes)))
+        return st;
+    if (!req->length)
+        return AES_OK;
+    if (ctx->device == AES_DEVICE_NONE)
+        return AES_ERR_DEVICE;
+    HIP_TRY(hipSetDevice(ctx->device));
+    // In place, a multi-tile CBC decryption stays in one wave, which carries
+    // each predecessor block in registers before overwriting it.
+    uint32_t tile = ctx->tile_bytes;
+    if (req->op == AES_OP_CBC_DEC && d_in == d_out && req->length > tile)
+        tile = (uint32_t)req->length;
+    const int e = launch_request(*req, tile, d_scheds, n_scheds, ctx->d_timg, d_in, d_out,
+                                 ctx->n_cu, stream);
+    if (e)
+        return hip_fail((hipError_t)e);
+    return AES_OK;
+}
+
+// -------------------------------------------------------------- HIP graphs
+
+namespace {
+
+int capture_stream(aes_ctx *ctx) {
+    if (!ctx->capture)
+        HIP_TRY(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+    return AES_OK;
+}
+
+// Ends a capture on ctx->capture and instantiates it into *out.
+int finish_capture(aes_ctx *ctx, int launch_status, uint64_t nodes, aes_graph_t **out) {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx->capture, &g);
+    if (launch_status) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return launch_status;
+    }
+    if (e != hipSuccess)
+        return hip_fail(e);
+    aes_graph *gr = new (std::nothrow) aes_graph();
+    if (!gr) {
+        (void)hipGraphDestroy(g);
+        return AES_ERR_NOMEM;
+    }
+    gr->graph = g;
+    gr->device = ctx->device;
+    gr->n_nodes = nodes;
+    if ((e = hipGraphInstantiate(&gr->exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        delete gr;
+        return hip_fail(e);
+    }
+    *out = gr;
+    return AES_OK;
+}
+
+}  // namespace
+
+int aes_plan_graph(aes_plan_t *plan, const aes_schedule_t *d_scheds, const uint8_t *d_in,
+                   uint8_t *d_out, aes_graph_t **out) {
+    if (!plan || !out)
+        return AES_ERR_ARG;
+    *out = nullptr;
+    aes_ctx *ctx = plan->ctx;
+    const uint64_t n = plan->n_dec + plan->n_ctr + plan->n_chain;
+    int st = check_buffers(d_in, d_out, plan->buf_bytes, n, d_scheds);
+    if (st)
+        return st;
+    if (ctx->device == AES_DEVICE_NONE)
+        return AES_ERR_DEVICE;
+    HIP_TRY(hipSetDevice(ctx->device));
+    if ((st = capture_stream(ctx)))
+        return st;
+    HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+    st = plan->p.payload ? launch_planned(ctx, view_of(plan->p, plan->d_units), d_scheds,
+                                          plan->n_scheds, d_in, d_out, ctx->capture)
+                         : AES_OK;
+    return finish_capture(ctx, st, 1, out);
+}
+
+int aes_requests_graph(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+                       const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
+                       const aes_req_t *reqs, uint64_t n_reqs, aes_graph_t **out) {
+    if (!ctx || !out)
+        return AES_ERR_ARG;
+    *out = nullptr;
+    int st = check_buffers(d_in, d_out, buf_bytes, n_reqs, d_scheds);
+    if (st)
+        return st;
+    if ((st = validate(reqs, n_reqs, n_scheds, buf_bytes)))
+        return st;
+    if (ctx->device == AES_DEVICE_NONE)
+        return AES_ERR_DEVICE;
+    HIP_TRY(hipSetDevice(ctx->device));
+    if ((st = capture_stream(ctx)))
+        return st;
+    HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+    uint64_t nodes = 0;
+    for (uint64_t i = 0; i < n_reqs && !st; i++) {
+        if (!reqs[i].length)
+            continue;
+        st = aes_request_launch(ctx, d_scheds, n_scheds, d_in, d_out, buf_bytes, &reqs[i],
+                                ctx->capture);
+        nodes++;
+    }
+    return finish_capture(ctx, st, nodes, out);
+}
+
+int aes_graph_launch(aes_graph_t *g, void *stream) {
+    if (!g)
+        return AES_ERR_ARG;
+    HIP_TRY(hipSetDevice(g->device));
+    HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return AES_OK;
+}
+
+void aes_graph_destroy(aes_graph_t *g) {
+    if (!g)
+        return;
+    (void)hipSetDevice(g->device);
+    if (g->exec)
+        (void)hipGraphExecDestroy(g->exec);
+    if (g->graph)
+        (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+// ----------------------------------------------------------------- tuning
+
+namespace {
+
+// Median time in ms of `iters` launches of plan (after one warm-up).
+int time_plan(aes_plan *plan, const aes_schedule_t *d_scheds, const uint8_t *d_in,
+              uint8_t *d_out, int iters, double *ms_out) {
+    aes_ctx *ctx = plan->ctx;
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    std::vector<double> ms;
+    int st = AES_OK;
+    for (int i = 0; i <= iters && !st; i++) {
+        hipError_t e = hipEventRecord(a, ctx->capture);
+        if (e == hipSuccess) {
+            st = launch_planned(ctx, view_of(plan->p, plan->d_units), d_scheds, plan->n_scheds,
+                                d_in, d_out, ctx->capture);
+            if (!st)
+                e = hipEventRecord(b, ctx->capture);
+        }
+        if (!st && e == hipSuccess)
+            e = hipEventSynchronize(b);
+        if (!st && e != hipSuccess)
+            st = hip_fail(e);
+        float t = 0.f;
+        if (!st && (e = hipEventElapsedTime(&t, a, b)) != hipSuccess)
+            st = hip_fail(e);
+        if (!st && i > 0)
+            ms.push_back(t);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st)
+        return st;
+    std::sort(ms.begin(), ms.end());
+    *ms_out = ms[ms.size() / 2];
+    return AES_OK;
+}
+
+}  // namespace
+
+int aes_tune(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_scheds,
+             uint64_t buf_bytes, const aes_schedule_t *d_scheds, const uint8_t *d_in,
+             uint8_t *d_out, uint32_t iters, aes_launch_config_t *best_out) {
+    if (!ctx || (n_reqs && !reqs) || iters < 1 || iters > 1000)
+        return AES_ERR_ARG;
+    int st = check_buffers(d_in, d_out, buf_bytes, n_reqs, d_scheds);
+    if (st)
+        return st;
+    if (n_reqs && d_in == d_out)
+        return AES_ERR_OVERLAP;  // repeated runs must not feed on their own output
+    if ((st = validate(reqs, n_reqs, n_scheds, buf_bytes)))
+        return st;
+    if (ctx->device == AES_DEVICE_NONE)
+        return AES_ERR_DEVICE;
+    HIP_TRY(hipSetDevice(ctx->device));
+    if ((st = capture_stream(ctx)))
+        return st;
+    aes_launch_config_t best;
+    aes_ctx_get_config(ctx, &best);
+    double best_ms = 1e30;
+    // One candidate: set it, (re)plan when the tile size changed, time it.
+    aes_plan *plan = nullptr;
+    uint32_t plan_tile = 0;
+    auto trial = [&](const aes_launch_config_t &c) -> int {
+        int s2 = aes_ctx_set_config(ctx, &c);
+        if (s2)
+            return AES_OK;  // shape not available: skip
+        if (!plan || plan_tile != c.tile_bytes) {
+            aes_plan_destroy(plan);
+            plan = nullptr;
+            if ((s2 = aes_plan_create(ctx, reqs, n_reqs, n_scheds, buf_bytes, &plan)))
+                return s2;
+            plan_tile = c.tile_bytes;
+        }
+        double ms = 0;
+        if ((s2 = time_plan(plan, d_scheds, d_in, d_out, (int)iters, &ms)))
+            return s2;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+        return AES_OK;
+    };
+    // Coordinate descent: tile size, then each kernel's shape, then the chain
+    // lanes and the fusion switch, each from the best point so far.
+    aes_launch_config_t c = best;
+    st = trial(c);
+    const uint32_t tiles[] = {4096, 8192, 16384};
+    for (uint32_t t : tiles) {
+        if (st)
+            break;
+        c = best;
+        c.tile_bytes = t;
+        st = trial(c);
+    }
+    const uint32_t shapes[][2] = {{1, 1024}, {2, 1024}, {2, 512}, {4, 512}, {4, 256}, {1, 512}};
+    for (auto &sh : shapes) {
+        if (st)
+            break;
+        c = best;
+        c.ctr_nb = c.dec_nb = sh[0];
+        c.ctr_wg = c.dec_wg = sh[1];
+        if (c.mixed_nb != 1 && sh[0] == 1)
+            c.mixed_nb = 1;
+        else if (sh[0] >= 2)
+            c.mixed_nb = 2;
+        st = trial(c);
+    }
+    const uint32_t lanes[] = {16, 32, 64};
+    for (uint32_t l : lanes) {
+        if (st)
+            break;
+        c = best;
+        c.chain_lanes = l;
+        st = trial(c);
+    }
+    for (uint32_t f = 0; f <= 1 && !st; f++) {
+        c = best;
+        c.fuse = f;
+        st = trial(c);
+    }
+    aes_plan_destroy(plan);
+    (void)aes_ctx_set_config(ctx, &best);
+    if (st)
+        return st;
+    if (best_out)
+        *best_out = best;
+    return AES_OK;
 }
 
 }  // extern "C"

@@ -230,37 +230,23 @@ __device__ __forceinline__ void ctr_unit(const uint32_t *lds, uint32_t L0, uint3
     }
 }
 
-template <int NB, int WG>
-__global__ __launch_bounds__(WG) void k_ctr_tiles(const Unit *__restrict__ units,
-                                                  uint32_t n_units,
-                                                  const aes_schedule_t *__restrict__ sched,
-                                                  uint32_t n_sched,
-                                                  const uint32_t *__restrict__ timg,
-                                                  const uint4 *__restrict__ preds,
-                                                  const uint8_t *in, uint8_t *out) {
-    __shared__ uint32_t lds[LDS_ENC_WORDS];
-    fill_tables<false>(lds, timg);
-    __syncthreads();
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t L0 = (lane & 31u) << 2;
-    const uint32_t L1 = L0 | 0x10000u;
-    const uint32_t wpb = blockDim.x >> 6;
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
-    const uint32_t nw = gridDim.x * wpb;
-    for (uint32_t u = wave; u < n_units; u += nw) {
-        const Unit un = units[u];
-        const uint32_t key = un.meta & META_KEY_MASK;
-        if (key >= n_sched)
-            continue;
-        const aes_schedule_t *ks = sched + key;
-        const uint32_t nr = ks->nr;
-        if (nr == 10)
-            ctr_unit<NB, 10>(lds, L0, L1, lane, un, ks->ek, in, out);
-        else if (nr == 12)
-            ctr_unit<NB, 12>(lds, L0, L1, lane, un, ks->ek, in, out);
-        else if (nr == 14)
-            ctr_unit<NB, 14>(lds, L0, L1, lane, un, ks->ek, in, out);
-    }
+// Key checks and round-count dispatch for one CTR unit (wave-uniform).
+template <int NB>
+__device__ __forceinline__ void run_ctr_unit(const uint32_t *lds, uint32_t L0, uint32_t L1,
+                                             uint32_t lane, const Unit &un,
+                                             const aes_schedule_t *__restrict__ sched,
+                                             uint32_t n_sched, const uint8_t *in, uint8_t *out) {
+    const uint32_t key = un.meta & META_KEY_MASK;
+    if (key >= n_sched)
+        return;
+    const aes_schedule_t *ks = sched + key;
+    const uint32_t nr = ks->nr;
+    if (nr == 10)
+        ctr_unit<NB, 10>(lds, L0, L1, lane, un, ks->ek, in, out);
+    else if (nr == 12)
+        ctr_unit<NB, 12>(lds, L0, L1, lane, un, ks->ek, in, out);
+    else if (nr == 14)
+        ctr_unit<NB, 14>(lds, L0, L1, lane, un, ks->ek, in, out);
 }
 
 // ------------------------------------------------------- CBC-decrypt tiles
@@ -328,39 +314,23 @@ __device__ __forceinline__ void cbcdec_unit(const uint32_t *lds, uint32_t L0, ui
     }
 }
 
-template <int NB, int WG>
-__global__ __launch_bounds__(WG) void k_cbcdec_tiles(const Unit *__restrict__ units,
-                                                       uint32_t n_units,
-                                                       const aes_schedule_t *__restrict__ sched,
-                                                       uint32_t n_sched,
-                                                       const uint32_t *__restrict__ timg,
-                                                       const uint4 *__restrict__ preds,
-                                                       const uint8_t *in, uint8_t *out) {
-    __shared__ uint32_t lds[LDS_DEC_WORDS];
-    fill_tables<true>(lds, timg);
-    __syncthreads();
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t L0 = (lane & 31u) << 2;
-    const uint32_t L1 = L0 | 0x10000u;
-    const uint32_t L2 = L0 | SI_BASE;
-    const uint32_t wpb = blockDim.x >> 6;
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
-    const uint32_t nw = gridDim.x * wpb;
-    for (uint32_t u = wave; u < n_units; u += nw) {
-        const Unit un = units[u];
-        const uint32_t key = un.meta & META_KEY_MASK;
-        if (key >= n_sched)
-            continue;
-        const aes_schedule_t *ks = sched + key;
-        const uint4 *snap = preds ? preds + u : nullptr;
-        const uint32_t nr = ks->nr;
-        if (nr == 10)
-            cbcdec_unit<NB, 10>(lds, L0, L1, L2, lane, un, snap, ks->dk, in, out);
-        else if (nr == 12)
-            cbcdec_unit<NB, 12>(lds, L0, L1, L2, lane, un, snap, ks->dk, in, out);
-        else if (nr == 14)
-            cbcdec_unit<NB, 14>(lds, L0, L1, L2, lane, un, snap, ks->dk, in, out);
-    }
+template <int NB>
+__device__ __forceinline__ void run_dec_unit(const uint32_t *lds, uint32_t L0, uint32_t L1,
+                                             uint32_t L2, uint32_t lane, const Unit &un,
+                                             const uint4 *snap,
+                                             const aes_schedule_t *__restrict__ sched,
+                                             uint32_t n_sched, const uint8_t *in, uint8_t *out) {
+    const uint32_t key = un.meta & META_KEY_MASK;
+    if (key >= n_sched)
+        return;
+    const aes_schedule_t *ks = sched + key;
+    const uint32_t nr = ks->nr;
+    if (nr == 10)
+        cbcdec_unit<NB, 10>(lds, L0, L1, L2, lane, un, snap, ks->dk, in, out);
+    else if (nr == 12)
+        cbcdec_unit<NB, 12>(lds, L0, L1, L2, lane, un, snap, ks->dk, in, out);
+    else if (nr == 14)
+        cbcdec_unit<NB, 14>(lds, L0, L1, L2, lane, un, snap, ks->dk, in, out);
 }
 
 // ------------------------------------------------------- CBC-encrypt chains
@@ -416,32 +386,202 @@ __device__ __forceinline__ void chain_run(const uint32_t *lds, uint32_t L0, uint
     }
 }
 
-__global__ __launch_bounds__(1024) void k_cbcenc_chains(const Unit *__restrict__ units,
-                                                        uint32_t n_units,
-                                                        const aes_schedule_t *__restrict__ sched,
-                                                        uint32_t n_sched,
-                                                        const uint32_t *__restrict__ timg,
-                                                        const uint8_t *in, uint8_t *out) {
+// One chain per lane; lanes of one wave may have different keys and lengths.
+__device__ __forceinline__ void run_chain(const uint32_t *lds, uint32_t L0, uint32_t L1,
+                                          const Unit &un, const aes_schedule_t *__restrict__ sched,
+                                          uint32_t n_sched, const uint8_t *in, uint8_t *out) {
+    const uint32_t key = un.meta & META_KEY_MASK;
+    if (key >= n_sched)
+        return;
+    const aes_schedule_t *ks = sched + key;
+    const uint32_t nr = ks->nr;
+    if (nr == 10)
+        chain_run<10>(lds, L0, L1, un, ks->ek, in, out);
+    else if (nr == 12)
+        chain_run<12>(lds, L0, L1, un, ks->ek, in, out);
+    else if (nr == 14)
+        chain_run<14>(lds, L0, L1, un, ks->ek, in, out);
+}
+
+// Chains of a wave: `cl` active lanes per wave (spreading few chains over more
+// waves and compute units lowers nothing but the per-CU contention; each lane
+// is still one serial chain).  Wave e takes chains e*cl + lane, then strides.
+__device__ __forceinline__ void chain_loop(const uint32_t *lds, uint32_t L0, uint32_t L1,
+                                           uint32_t lane, uint32_t e, uint32_t n_waves,
+                                           uint32_t cl, const Unit *__restrict__ chains,
+                                           uint32_t n_chain,
+                                           const aes_schedule_t *__restrict__ sched,
+                                           uint32_t n_sched, const uint8_t *in, uint8_t *out) {
+    if (lane >= cl)
+        return;
+    for (uint64_t c = (uint64_t)e * cl + lane; c < n_chain; c += (uint64_t)n_waves * cl) {
+        const Unit un = chains[c];
+        run_chain(lds, L0, L1, un, sched, n_sched, in, out);
+    }
+}
+
+// ------------------------------------------------------------ tile kernels
+
+// Parallel-mode kernel: one table set in LDS per workgroup; wave w works
+// units w, w + W, ... (W waves in the grid).
+template <bool DEC, int NB, int WG>
+__global__ __launch_bounds__(WG) void k_tiles(const Unit *__restrict__ units, uint32_t n_units,
+                                              const aes_schedule_t *__restrict__ sched,
+                                              uint32_t n_sched, const uint32_t *__restrict__ timg,
+                                              const uint4 *__restrict__ preds, const uint8_t *in,
+                                              uint8_t *out) {
+    __shared__ uint32_t lds[DEC ? LDS_DEC_WORDS : LDS_ENC_WORDS];
+    fill_tables<DEC>(lds, timg);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t L0 = (lane & 31u) << 2;
+    const uint32_t L1 = L0 | 0x10000u;
+    const uint32_t L2 = L0 | SI_BASE;
+    const uint32_t wpb = blockDim.x >> 6;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
+    const uint32_t nw = gridDim.x * wpb;
+    for (uint32_t u = wave; u < n_units; u += nw) {
+        const Unit un = units[u];
+        if (DEC)
+            run_dec_unit<NB>(lds, L0, L1, L2, lane, un, preds ? preds + u : nullptr, sched,
+                             n_sched, in, out);
+        else
+            run_ctr_unit<NB>(lds, L0, L1, lane, un, sched, n_sched, in, out);
+    }
+}
+
+// Wave numbering that spreads consecutive waves over workgroups first.
+__device__ __forceinline__ uint32_t spread_wave(uint32_t wg, uint32_t n_wg) {
+    return __builtin_amdgcn_readfirstlane((threadIdx.x >> 6) * n_wg + wg);
+}
+
+__global__ __launch_bounds__(1024) void k_chains(const Unit *__restrict__ chains,
+                                                 uint32_t n_chain, uint32_t cl,
+                                                 const aes_schedule_t *__restrict__ sched,
+                                                 uint32_t n_sched,
+                                                 const uint32_t *__restrict__ timg,
+                                                 const uint8_t *in, uint8_t *out) {
     __shared__ uint32_t lds[LDS_ENC_WORDS];
     fill_tables<false>(lds, timg);
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t L0 = (lane & 31u) << 2;
     const uint32_t L1 = L0 | 0x10000u;
-    const uint32_t nthreads = gridDim.x * blockDim.x;
-    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n_units; u += nthreads) {
-        const Unit un = units[u];
-        const uint32_t key = un.meta & META_KEY_MASK;
-        if (key >= n_sched)
-            continue;
-        const aes_schedule_t *ks = sched + key;
-        const uint32_t nr = ks->nr;
-        if (nr == 10)
-            chain_run<10>(lds, L0, L1, un, ks->ek, in, out);
-        else if (nr == 12)
-            chain_run<12>(lds, L0, L1, un, ks->ek, in, out);
-        else if (nr == 14)
-            chain_run<14>(lds, L0, L1, un, ks->ek, in, out);
+    const uint32_t n_waves = gridDim.x * (blockDim.x >> 6);
+    chain_loop(lds, L0, L1, lane, spread_wave(blockIdx.x, gridDim.x), n_waves, cl, chains,
+               n_chain, sched, n_sched, in, out);
+}
+
+// ----------------------------------------------------- one fused launch
+
+// A whole mixed batch in one launch.  Workgroups [0, n_dec_wg) hold the
+// decryption tables and work the CBC-decrypt tiles; the others hold the
+// encryption tables, start the CBC-encrypt chains (the long serial work)
+// on their first waves, and every encryption wave then works CTR tiles.
+template <int NB>
+__global__ __launch_bounds__(1024) void k_mixed(MixedArgs a) {
+    __shared__ uint32_t lds[LDS_DEC_WORDS];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t L0 = (lane & 31u) << 2;
+    const uint32_t L1 = L0 | 0x10000u;
+    const uint32_t L2 = L0 | SI_BASE;
+    const uint32_t wpb = blockDim.x >> 6;
+    if (blockIdx.x < a.n_dec_wg) {
+        fill_tables<true>(lds, a.timg);
+        __syncthreads();
+        const uint32_t nw = a.n_dec_wg * wpb;
+        for (uint32_t u = spread_wave(blockIdx.x, a.n_dec_wg); u < a.n_dec; u += nw) {
+            const Unit un = a.dec[u];
+            run_dec_unit<NB>(lds, L0, L1, L2, lane, un,
+                             a.preds ? reinterpret_cast<const uint4 *>(a.preds) + u : nullptr,
+                             a.sched, a.n_sched, a.in, a.out);
+        }
+        return;
+    }
+    fill_tables<false>(lds, a.timg);
+    __syncthreads();
+    const uint32_t n_enc_wg = gridDim.x - a.n_dec_wg;
+    const uint32_t e = spread_wave(blockIdx.x - a.n_dec_wg, n_enc_wg);
+    const uint32_t nw = n_enc_wg * wpb;
+    if (a.n_chain) {
+        const uint32_t chain_waves = (uint32_t)(((uint64_t)a.n_chain + a.chain_lanes - 1) /
+                                                a.chain_lanes);
+        const uint32_t cw = chain_waves < nw ? chain_waves : nw;
+        if (e < cw)
+            chain_loop(lds, L0, L1, lane, e, cw, a.chain_lanes, a.chains, a.n_chain, a.sched,
+                       a.n_sched, a.in, a.out);
+    }
+    for (uint32_t u = e; u < a.n_ctr; u += nw) {
+        const Unit un = a.ctr[u];
+        run_ctr_unit<NB>(lds, L0, L1, lane, un, a.sched, a.n_sched, a.in, a.out);
+    }
+}
+
+// ------------------------------------------------- one request per launch
+
+// Unit t of a single request passed by value (the per-request launch form).
+__device__ __forceinline__ Unit request_unit(const aes_req_t &r, uint32_t t, uint32_t tile) {
+    Unit u;
+    const uint64_t pos = (uint64_t)t * tile;
+    u.off = r.offset + pos;
+    const uint64_t left = r.length - pos;
+    u.nbytes = (uint32_t)(left < tile ? left : tile);
+    u.meta = r.key_idx | (r.op << META_OP_SHIFT);
+    uint32_t w[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+        w[i] = (uint32_t)r.iv[4 * i] | ((uint32_t)r.iv[4 * i + 1] << 8) |
+               ((uint32_t)r.iv[4 * i + 2] << 16) | ((uint32_t)r.iv[4 * i + 3] << 24);
+    if (r.op == AES_OP_CTR) {
+        // initial counter: bytes 8..15 of T1 big-endian, plus the tile's first block
+        const uint64_t c0 = ((uint64_t)__builtin_bswap32(w[2]) << 32) | __builtin_bswap32(w[3]);
+        const uint64_t c = c0 + pos / 16;
+        u.w[0] = w[0];
+        u.w[1] = w[1];
+        u.w[2] = (uint32_t)c;
+        u.w[3] = (uint32_t)(c >> 32);
+    } else if (t == 0 || r.op == AES_OP_CBC_ENC) {
+        u.w[0] = w[0];
+        u.w[1] = w[1];
+        u.w[2] = w[2];
+        u.w[3] = w[3];
+    } else {
+        u.meta |= FLAG_PRED_IN;
+        u.w[0] = u.w[1] = u.w[2] = u.w[3] = 0u;
+    }
+    return u;
+}
+
+template <bool DEC, int NB>
+__global__ __launch_bounds__(256) void k_request(aes_req_t r, uint32_t tile,
+                                                 const aes_schedule_t *__restrict__ sched,
+                                                 uint32_t n_sched,
+                                                 const uint32_t *__restrict__ timg,
+                                                 const uint8_t *in, uint8_t *out) {
+    __shared__ uint32_t lds[DEC ? LDS_DEC_WORDS : LDS_ENC_WORDS];
+    fill_tables<DEC>(lds, timg);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t L0 = (lane & 31u) << 2;
+    const uint32_t L1 = L0 | 0x10000u;
+    const uint32_t L2 = L0 | SI_BASE;
+    if (!DEC && r.op == AES_OP_CBC_ENC) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            const Unit un = request_unit(r, 0, (uint32_t)r.length);
+            run_chain(lds, L0, L1, un, sched, n_sched, in, out);
+        }
+        return;
+    }
+    const uint32_t wpb = blockDim.x >> 6;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
+    const uint32_t nw = gridDim.x * wpb;
+    const uint32_t n_units = (uint32_t)((r.length + tile - 1) / tile);
+    for (uint32_t t = wave; t < n_units; t += nw) {
+        const Unit un = request_unit(r, t, tile);
+        if (DEC)
+            run_dec_unit<NB>(lds, L0, L1, L2, lane, un, nullptr, sched, n_sched, in, out);
+        else
+            run_ctr_unit<NB>(lds, L0, L1, lane, un, sched, n_sched, in, out);
     }
 }
 
@@ -477,10 +617,10 @@ template <bool DEC>
 static TileKernel pick_tile_kernel(int nb, int wg) {
 #define AESGPU_TK(NB_, WG_)                                                                     \
     if (nb == NB_ && wg <= WG_)                                                                 \
-        return DEC ? (TileKernel)&k_cbcdec_tiles<NB_, WG_> : (TileKernel)&k_ctr_tiles<NB_, WG_>;
+        return (TileKernel)&k_tiles<DEC, NB_, WG_>;
     AESGPU_TK(1, 256) AESGPU_TK(1, 512) AESGPU_TK(1, 1024)
     AESGPU_TK(2, 256) AESGPU_TK(2, 512) AESGPU_TK(2, 1024)
-    AESGPU_TK(4, 256) AESGPU_TK(4, 512) AESGPU_TK(4, 1024)
+    AESGPU_TK(4, 256) AESGPU_TK(4, 512)
 #undef AESGPU_TK
     return nullptr;
 }
@@ -518,19 +658,63 @@ int launch_cbcdec_tiles(const Unit *d_units, uint32_t n_units, const aes_schedul
                         d_sched, n_sched, d_timg, d_preds, d_in, d_out, cfg, n_cu, stream);
 }
 
+static uint32_t chain_waves_needed(uint32_t n_chain, uint32_t cl) {
+    return (uint32_t)(((uint64_t)n_chain + cl - 1) / cl);
+}
+
 int launch_cbcenc_chains(const Unit *d_units, uint32_t n_units, const aes_schedule_t *d_sched,
                          uint32_t n_sched, const uint32_t *d_timg, const uint8_t *d_in,
                          uint8_t *d_out, const ChainLaunch &cfg, int n_cu, void *stream) {
     if (!n_units)
         return hipSuccess;
-    int grid = cfg.grid;
-    if (grid <= 0) {
-        grid = (int)((n_units + cfg.wg_threads - 1) / cfg.wg_threads);
-        if (grid > n_cu)
-            grid = n_cu;
+    const uint32_t cl = cfg.lanes < 1 ? 64u : (cfg.lanes > 64 ? 64u : (uint32_t)cfg.lanes);
+    const int wpb = cfg.wg_threads / 64;
+    const uint32_t waves = chain_waves_needed(n_units, cl);
+    int grid = cfg.grid > 0 ? cfg.grid : (int)((waves + wpb - 1) / wpb);
+    if (grid > n_cu && cfg.grid <= 0)
+        grid = n_cu;
+    // Fewer waves than compute units: one wave per workgroup spreads them out.
+    int threads = cfg.wg_threads;
+    if (cfg.grid <= 0 && waves < (uint32_t)n_cu * wpb) {
+        const uint32_t per_cu = (waves + n_cu - 1) / n_cu;
+        threads = 64 * (int)(per_cu < 1 ? 1 : per_cu);
+        grid = (int)((waves + per_cu - 1) / per_cu);
     }
-    hipLaunchKernelGGL(k_cbcenc_chains, dim3(grid), dim3(cfg.wg_threads), 0, (hipStream_t)stream,
-                       d_units, n_units, d_sched, n_sched, d_timg, d_in, d_out);
+    hipLaunchKernelGGL(k_chains, dim3(grid < 1 ? 1 : grid), dim3(threads), 0,
+                       (hipStream_t)stream, d_units, n_units, cl, d_sched, n_sched, d_timg, d_in,
+                       d_out);
+    return hipGetLastError();
+}
+
+int launch_mixed(const MixedArgs &a, int nb, int grid, void *stream) {
+    if (!a.n_dec && !a.n_ctr && !a.n_chain)
+        return hipSuccess;
+    void (*k)(MixedArgs) = nb == 1 ? &k_mixed<1> : (nb == 2 ? &k_mixed<2> : nullptr);
+    if (!k || grid < 1 || (a.n_dec && a.n_dec_wg < 1) ||
+        ((a.n_ctr || a.n_chain) && (uint32_t)grid <= a.n_dec_wg) || a.chain_lanes < 1 ||
+        a.chain_lanes > 64)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(1024), 0, (hipStream_t)stream, a);
+    return hipGetLastError();
+}
+
+int launch_request(const aes_req_t &r, uint32_t tile, const aes_schedule_t *d_sched,
+                   uint32_t n_sched, const uint32_t *d_timg, const uint8_t *d_in,
+                   uint8_t *d_out, int n_cu, void *stream) {
+    if (!r.length)
+        return hipSuccess;
+    const uint32_t n_units = (uint32_t)((r.length + tile - 1) / tile);
+    int grid = (int)((n_units + 3) / 4);
+    if (grid > n_cu)
+        grid = n_cu;
+    if (r.op == AES_OP_CBC_ENC)
+        grid = 1;
+    if (r.op == AES_OP_CBC_DEC)
+        hipLaunchKernelGGL((k_request<true, 2>), dim3(grid), dim3(256), 0, (hipStream_t)stream, r,
+                           tile, d_sched, n_sched, d_timg, d_in, d_out);
+    else
+        hipLaunchKernelGGL((k_request<false, 2>), dim3(grid), dim3(r.op == AES_OP_CBC_ENC ? 64 : 256),
+                           0, (hipStream_t)stream, r, tile, d_sched, n_sched, d_timg, d_in, d_out);
     return hipGetLastError();
 }
 

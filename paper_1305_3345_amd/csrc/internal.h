@@ -41,8 +41,25 @@ struct TileLaunch {
 bool tile_shape_supported(int nb, int wg_threads);
 
 struct ChainLaunch {
-    int wg_threads = 64;
-    int grid = 0;  // 0 = as many as the chains need
+    int wg_threads = 256;
+    int lanes = 64;  // active lanes (chains) per wave
+    int grid = 0;    // 0 = as many as the chains need, at most one per compute unit
+};
+
+// Arguments of the fused mixed-batch kernel (one launch for all three ops).
+struct MixedArgs {
+    const Unit *dec;        // CBC-decrypt tiles
+    const Unit *ctr;        // CTR tiles
+    const Unit *chains;     // CBC-encrypt chains, longest first
+    const uint32_t *preds;  // NULL or 4 words per CBC-decrypt tile (in-place snapshots)
+    const aes_schedule_t *sched;
+    const uint32_t *timg;
+    const uint8_t *in;
+    uint8_t *out;
+    uint32_t n_dec, n_ctr, n_chain;
+    uint32_t n_sched;
+    uint32_t n_dec_wg;      // workgroups [0, n_dec_wg) hold the decryption tables
+    uint32_t chain_lanes;   // active lanes per chain wave
 };
 
 // Host-side launchers (aes_kernels.hip).  Each returns a hipError_t value.
@@ -58,6 +75,13 @@ int launch_cbcdec_tiles(const Unit *d_units, uint32_t n_units, const aes_schedul
 int launch_cbcenc_chains(const Unit *d_units, uint32_t n_units, const aes_schedule_t *d_sched,
                          uint32_t n_sched, const uint32_t *d_timg, const uint8_t *d_in,
                          uint8_t *d_out, const ChainLaunch &cfg, int n_cu, void *stream);
+// One launch over a mixed batch (nb = 1 or 2; 1024-thread workgroups).
+int launch_mixed(const MixedArgs &a, int nb, int grid, void *stream);
+// One request passed by value (the per-request launch form); tile = bytes per
+// unit (the whole request length keeps an in-place CBC decryption in one wave).
+int launch_request(const aes_req_t &r, uint32_t tile, const aes_schedule_t *d_sched,
+                   uint32_t n_sched, const uint32_t *d_timg, const uint8_t *d_in,
+                   uint8_t *d_out, int n_cu, void *stream);
 // In-place CBC decryption: copies in[off-16, off) of every FLAG_PRED_IN unit u
 // to d_preds[16u..16u+15] before the tile kernel overwrites those bytes.
 int launch_snapshot_preds(const Unit *d_units, uint32_t n_units, const uint8_t *d_in,
