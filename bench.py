@@ -40,6 +40,8 @@ def parse():
                     help="iterations of the host-metadata single-call form (0 = skip)")
     ap.add_argument("--runs", default="cbc_dec_128,ctr_128,cbc_dec_256,ctr_256",
                     help="comma-separated subset of the step's runs (for profiling)")
+    ap.add_argument("--skip-batched", action="store_true",
+                    help="skip the mixed-batch (10,000 uneven requests) measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also copy the 256 MiB input once device-to-device (a kernel of "
                          "known traffic for scaling hardware byte counters)")
@@ -70,6 +72,92 @@ def cpu_baseline(sample_pages: int):
             "kind": "oracle",
             "sample": f"first {sample_pages} pages of each of the 4 runs of a step "
                       f"({total >> 20} MiB), same keys/IVs/bytes, {secs:.1f} s"}
+
+
+def time_gpu(fn, iters, stream):
+    """Median milliseconds of fn() over iters runs after one warm-up (HIP events)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(iters):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    ms.sort()
+    return ms[len(ms) // 2]
+
+
+def bench_batched(dev, iters=3):
+    """The batched form: 10,000 uneven requests (4 KiB..1 MiB, mixed ops, 64
+    keys of 128/256 bits) as one autotuned fused launch, against one kernel
+    launch per request and a HIP graph of those launches (on the requests of
+    the parallel modes; the serial CBC-encrypt chains make per-request
+    launches of the whole mix take tens of seconds), plus the chain floor
+    (the longest CBC-encrypt chain alone)."""
+    import numpy as np
+    import torch
+
+    from paper_1305_3345_amd import aesgpu
+    from synth import gen, workloads
+
+    wl = workloads.config3()
+    nbytes = wl.buf_bytes
+    d_in = gen.bytes_torch(0, gen.STREAM_DATA, (nbytes + 7) // 8 * 8, dev)[:nbytes]
+    d_out = torch.empty_like(d_in)
+    d_s = aesgpu.schedules_to_device(aesgpu.expand_keys(wl.keys, wl.key_bits), dev)
+    stream = torch.cuda.current_stream()
+    ctx = aesgpu.Context(0)
+    t0 = time.perf_counter()
+    cfg = aesgpu.tune(ctx, wl.reqs, d_s, d_in, d_out, iters=2)
+    tune_s = time.perf_counter() - t0
+    plan = aesgpu.Plan(ctx, wl.reqs, wl.keys.shape[0], nbytes)
+    info = plan.info()
+    full_ms = time_gpu(lambda: plan.launch(d_s, d_in, d_out, stream=stream), iters, stream)
+    g_plan = aesgpu.Graph.of_plan(plan, d_s, d_in, d_out)
+    full_graph_ms = time_gpu(lambda: g_plan.launch(stream), iters, stream)
+
+    enc = np.nonzero(wl.reqs["op"] == workloads.OP_CBC_ENC)[0]
+    longest = wl.reqs[enc[np.argmax(wl.reqs["length"][enc])]: enc[np.argmax(wl.reqs["length"][enc])] + 1]
+    p_long = aesgpu.Plan(ctx, longest, wl.keys.shape[0], nbytes)
+    chain_ms = time_gpu(lambda: p_long.launch(d_s, d_in, d_out, stream=stream), iters, stream)
+
+    par = wl.reqs[wl.reqs["op"] != workloads.OP_CBC_ENC]
+    par_bytes = int(par["length"].sum())
+    p_par = aesgpu.Plan(ctx, par, wl.keys.shape[0], nbytes)
+    par_batched_ms = time_gpu(lambda: p_par.launch(d_s, d_in, d_out, stream=stream), iters, stream)
+    par_each_ms = time_gpu(lambda: aesgpu.request_launches(ctx, d_s, d_in, d_out, par,
+                                                           stream=stream), iters, stream)
+    g_each = aesgpu.Graph.of_requests(ctx, d_s, d_in, d_out, par)
+    par_graph_ms = time_gpu(lambda: g_each.launch(stream), iters, stream)
+    for o in (g_plan, g_each, plan, p_long, p_par):
+        o.close()
+    ctx.close()
+    gbs = lambda b, ms: round(b / ms / 1e6, 1)
+    return {
+        "workload": f"{wl.reqs.size} requests, 4 KiB..1 MiB log-uniform, ops "
+                    f"{int((wl.reqs['op'] == 0).sum())} CBC-enc / {int((wl.reqs['op'] == 1).sum())} "
+                    f"CBC-dec / {int((wl.reqs['op'] == 2).sum())} CTR, 64 keys (128/256)",
+        "payload_bytes": info["payload_bytes"],
+        "tuned_config": cfg, "tune_s": round(tune_s, 2),
+        "one_launch_ms": round(full_ms, 3), "one_launch_gbs": gbs(info["payload_bytes"], full_ms),
+        "plan_graph_ms": round(full_graph_ms, 3),
+        "chain_floor_ms": round(chain_ms, 3),
+        "chain_floor_request_bytes": int(longest["length"][0]),
+        "parallel_subset": {
+            "requests": int(par.size), "payload_bytes": par_bytes,
+            "one_launch_gbs": gbs(par_bytes, par_batched_ms),
+            "per_request_launches_gbs": gbs(par_bytes, par_each_ms),
+            "per_request_graph_gbs": gbs(par_bytes, par_graph_ms),
+            "one_launch_ms": round(par_batched_ms, 3),
+            "per_request_launches_ms": round(par_each_ms, 3),
+            "per_request_graph_ms": round(par_graph_ms, 3),
+        },
+    }
 
 
 def main():
@@ -179,6 +267,10 @@ def main():
                     "note": "aes_cbc_decrypt_batch / aes_ctr_batch with host request arrays "
                             "(validation + planning + metadata upload in every call)"}
 
+    batched = None
+    if not args.skip_batched:
+        batched = bench_batched(dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(min(args.cpu_sample_pages, n_pages))
@@ -205,6 +297,7 @@ def main():
         "cpu_baseline": cpu,
         "per_run": per_run,
         "per_call": per_call,
+        "batched": batched,
     }
     for _, _, plan, _, _, _, _ in runs:
         plan.close()

@@ -254,6 +254,12 @@ int aes_request_launch(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t 
                        const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
                        const aes_req_t *req, void *stream);
 
+/* aes_request_launch for each of n_reqs requests in turn (all validated
+ * first, including disjointness), issued back to back on stream. */
+int aes_request_launches(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+                         const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
+                         const aes_req_t *reqs, uint64_t n_reqs, void *stream);
+
 /* An instantiated HIP graph owned by the library. */
 typedef struct aes_graph aes_graph_t;
 
@@ -267,6 +273,104 @@ int aes_requests_graph(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t 
 /* Launches a graph on stream.  Errors: AES_ERR_ARG, AES_ERR_DEVICE. */
 int aes_graph_launch(aes_graph_t *graph, void *stream);
 void aes_graph_destroy(aes_graph_t *graph);
+
+/* ------------------------------------------------------------------ serving */
+
+/* The serving form of paper sections 3.1-3.2: requests are posted one by one
+ * while the GPU runs, each gets a ticket, and completions come back as they
+ * finish (callback, poll, or blocking wait).  Two engines share this API:
+ *   AES_SERVE_PERSISTENT: the paper's Non-Stop Kernel -- one kernel launched
+ *     once (and again on demand after an idle exit) polls a ring of request
+ *     descriptors in pinned host-mapped memory, keeps the cipher tables in
+ *     LDS and the key schedules resident in HBM, splits each request into
+ *     work units that idle waves claim (continuous batching: requests that
+ *     arrive while others run are taken as soon as their descriptors land),
+ *     and writes each completion into host-mapped memory.  Requests larger
+ *     than max_request_bytes take a normal launch instead, as the paper's
+ *     NSK does for services that need more threads.
+ *   AES_SERVE_PER_LAUNCH: one kernel launch per request on a pool of
+ *     streams (the baseline the paper compares the NSK with).
+ * Payloads are device buffers owned by the caller (d_src, d_dst: equal or
+ * disjoint); they must stay valid until the request completes.  Admission:
+ * at most ring_slots requests and hbm_cap_bytes request bytes in flight;
+ * beyond that aes_server_submit returns AES_ERR_AGAIN. */
+typedef struct aes_server aes_server_t;
+
+enum { AES_SERVE_PERSISTENT = 0, AES_SERVE_PER_LAUNCH = 1 };
+
+typedef struct aes_server_config {
+    uint32_t mode;              /* AES_SERVE_PERSISTENT (default) or AES_SERVE_PER_LAUNCH */
+    uint32_t ring_slots;        /* power of two, 64..65536 (default 4096) */
+    uint32_t key_slots;         /* resident key schedules, 1..65536 (default 256) */
+    uint32_t n_workgroups;      /* persistent grid; 0 = compute units minus 16 */
+    uint32_t dec_workgroups;    /* of those, workgroups holding decryption tables; 0 = half */
+    uint32_t n_streams;         /* per-launch engine: stream pool (default 8) */
+    uint32_t queue_units;       /* persistent engine: device queue capacity in work units per
+                                   table set, power of two (default 65536) */
+    uint32_t idle_timeout_ms;   /* persistent kernel exits after this long without requests
+                                   (default 1000); the next submit launches it again */
+    uint64_t hbm_cap_bytes;     /* admission cap on in-flight request bytes (default 256 MiB) */
+    uint64_t max_request_bytes; /* larger requests take a normal launch (default 4 MiB) */
+    uint32_t reserved[8];
+} aes_server_config_t;
+
+/* One completion.  Times: host steady clock in ns (t_submit_ns when the
+ * request was posted -- or its intended arrival time in aes_server_replay --
+ * and t_done_ns when the host observed the completion); gpu_*_ticks are the
+ * device's 100 MHz clock when the persistent kernel dispatched the request
+ * and when its last unit finished (0 in the per-launch engine). */
+typedef struct aes_done {
+    uint64_t ticket;
+    int32_t status; /* AES_OK, or the request's error */
+    uint32_t units; /* work units the request was cut into (persistent engine) */
+    uint64_t t_submit_ns;
+    uint64_t t_done_ns;
+    uint64_t gpu_dispatch_ticks;
+    uint64_t gpu_done_ticks;
+} aes_done_t;
+
+/* Called on the library's completion thread; must not call back into the
+ * same server except aes_server_submit. */
+typedef void (*aes_done_cb)(const aes_done_t *done, void *user);
+
+typedef struct aes_server_stats {
+    uint64_t submitted, completed, rejected_again, fallbacks, kernel_launches;
+    uint64_t in_flight, in_flight_bytes;
+} aes_server_stats_t;
+
+/* cfg may be NULL (defaults).  Errors: AES_ERR_ARG, AES_ERR_DEVICE, AES_ERR_NOMEM. */
+int aes_server_create(aes_ctx_t *ctx, const aes_server_config_t *cfg, aes_server_t **out);
+/* Copies a schedule into resident slot `slot` (synchronously).  Allowed while
+ * nothing is in flight (else AES_ERR_STATE); a running persistent kernel is
+ * stopped first and relaunched by the next submit. */
+int aes_server_set_key(aes_server_t *srv, uint32_t slot, const aes_schedule_t *host_sched);
+/* Posts one request (paper section 3.2: buffers, a service request, an
+ * optional completion callback).  op and iv as in aes_req_t; length > 0,
+ * < 2^32, a multiple of 16 for CBC.  Sets *ticket.  Errors: AES_ERR_ARG,
+ * AES_ERR_LENGTH, AES_ERR_RANGE (key slot), AES_ERR_OVERLAP, AES_ERR_AGAIN
+ * (admission), AES_ERR_DEVICE. */
+int aes_server_submit(aes_server_t *srv, uint32_t op, uint32_t key_slot, const uint8_t iv[16],
+                      const uint8_t *d_src, uint8_t *d_dst, uint64_t length, aes_done_cb cb,
+                      void *user, uint64_t *ticket);
+/* Non-blocking: moves up to max finished completions (of requests posted
+ * without a callback) to out, oldest first. */
+int aes_server_poll(aes_server_t *srv, aes_done_t *out, uint32_t max, uint32_t *n_out);
+/* Blocks until `ticket` (posted without a callback) completes, then moves its
+ * completion to *out (may be NULL).  Errors: AES_ERR_TIMEOUT, AES_ERR_ARG
+ * (unknown ticket). */
+int aes_server_wait(aes_server_t *srv, uint64_t ticket, uint64_t timeout_ns, aes_done_t *out);
+/* Open-loop replay of a request trace: request i (offset into both bases,
+ * length, key slot in key_idx, op, iv) is posted at arrival_s[i] seconds
+ * after the call starts, retried while admission says AES_ERR_AGAIN; the call
+ * returns when all have completed, with out[i] its completion (t_submit_ns =
+ * the arrival time, so latency includes any admission wait). */
+int aes_server_replay(aes_server_t *srv, const aes_req_t *reqs, const double *arrival_s,
+                      uint64_t n, const uint8_t *d_src_base, uint8_t *d_dst_base,
+                      aes_done_t *out);
+int aes_server_stats(aes_server_t *srv, aes_server_stats_t *out);
+/* Waits (up to 10 s) for in-flight requests, stops the kernel and frees
+ * everything.  Returns AES_ERR_TIMEOUT if requests were still in flight. */
+int aes_server_destroy(aes_server_t *srv);
 
 #ifdef __cplusplus
 }

@@ -6,5 +6,5 @@ include/aesgpu.h); ``aesgpu`` is its ctypes binding.
 from . import aesgpu  # noqa: F401
 from .aesgpu import (AES_DEVICE_NONE, AES_OP_CBC_DEC, AES_OP_CBC_ENC, AES_OP_CTR,  # noqa: F401
                      AesError, Context, Graph, Plan, batch, cbc_decrypt_batch, cbc_encrypt_batch,
-                     ctr_batch, expand_key, expand_keys, request_launch,
+                     ctr_batch, expand_key, expand_keys, request_launch, Server,
                      schedules_to_device, tune)

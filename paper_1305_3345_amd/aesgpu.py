@@ -99,6 +99,7 @@ def lib():
             "aes_ctx_set_config": (i32, [p, p]),
             "aes_tune": (i32, [p, p, u64, u32, u64, p, p, p, u32, p]),
             "aes_request_launch": (i32, [p, p, u32, p, p, u64, p, p]),
+            "aes_request_launches": (i32, [p, p, u32, p, p, u64, p, u64, p]),
             "aes_plan_graph": (i32, [p, p, p, p, ctypes.POINTER(p)]),
             "aes_requests_graph": (i32, [p, p, u32, p, p, u64, p, u64, ctypes.POINTER(p)]),
             "aes_graph_launch": (i32, [p, p]),
@@ -331,6 +332,16 @@ def request_launch(ctx: Context, d_scheds, d_in, d_out, req, buf_bytes: int | No
            "aes_request_launch")
 
 
+def request_launches(ctx: Context, d_scheds, d_in, d_out, reqs: np.ndarray,
+                     buf_bytes: int | None = None, n_scheds: int | None = None, stream=None):
+    """aes_request_launches: one kernel launch per request, issued from C."""
+    reqs = np.ascontiguousarray(reqs, dtype=REQ_DTYPE)
+    bb = _nbytes(d_in) if buf_bytes is None else buf_bytes
+    _check(lib().aes_request_launches(ctx.handle, _ptr(d_scheds), _sched_count(d_scheds, n_scheds),
+                                      _ptr(d_in), _ptr(d_out), bb, reqs.ctypes.data, reqs.size,
+                                      _stream(stream)), "aes_request_launches")
+
+
 class Graph:
     """An instantiated HIP graph: aes_plan_graph / aes_requests_graph, launch, destroy."""
 
@@ -364,6 +375,148 @@ class Graph:
         if self.handle:
             lib().aes_graph_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ serving
+
+AES_SERVE_PERSISTENT = 0
+AES_SERVE_PER_LAUNCH = 1
+
+SERVER_CONFIG_DTYPE = np.dtype([("mode", "<u4"), ("ring_slots", "<u4"), ("key_slots", "<u4"),
+                                ("n_workgroups", "<u4"), ("dec_workgroups", "<u4"),
+                                ("n_streams", "<u4"), ("queue_units", "<u4"),
+                                ("idle_timeout_ms", "<u4"), ("hbm_cap_bytes", "<u8"),
+                                ("max_request_bytes", "<u8"), ("reserved", "<u4", (8,))])
+DONE_DTYPE = np.dtype([("ticket", "<u8"), ("status", "<i4"), ("units", "<u4"),
+                       ("t_submit_ns", "<u8"), ("t_done_ns", "<u8"),
+                       ("gpu_dispatch_ticks", "<u8"), ("gpu_done_ticks", "<u8")])
+STATS_NAMES = ("submitted", "completed", "rejected_again", "fallbacks", "kernel_launches",
+               "in_flight", "in_flight_bytes")
+assert SERVER_CONFIG_DTYPE.itemsize == 80 and DONE_DTYPE.itemsize == 48
+
+DONE_CB = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+_servers = None
+
+
+def _server_sig():
+    L = lib()
+    p = ctypes.c_void_p
+    u32, u64, i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    for name, res, args in (
+            ("aes_server_create", i32, [p, p, ctypes.POINTER(p)]),
+            ("aes_server_set_key", i32, [p, u32, p]),
+            ("aes_server_submit", i32, [p, u32, u32, p, p, p, u64, p, p, ctypes.POINTER(u64)]),
+            ("aes_server_poll", i32, [p, p, u32, ctypes.POINTER(u32)]),
+            ("aes_server_wait", i32, [p, u64, u64, p]),
+            ("aes_server_replay", i32, [p, p, p, u64, p, p, p]),
+            ("aes_server_stats", i32, [p, p]),
+            ("aes_server_destroy", i32, [p])):
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+class Server:
+    """aes_server_*: persistent-kernel (mode 0) or per-request-launch (mode 1) serving.
+
+    Keyword arguments set aes_server_config_t fields (0 = library default).
+    Always close() a server (or use it as a context manager): a persistent
+    kernel otherwise keeps running until its idle timeout.
+    """
+
+    def __init__(self, ctx: Context, **cfg):
+        global _servers
+        L = _server_sig()
+        c = np.zeros(1, SERVER_CONFIG_DTYPE)
+        for k, v in cfg.items():
+            c[0][k] = v
+        h = ctypes.c_void_p()
+        _check(L.aes_server_create(ctx.handle, c.ctypes.data, ctypes.byref(h)),
+               "aes_server_create")
+        self.handle = h.value
+        self.ctx = ctx
+        self._cbs = {}
+        if _servers is None:
+            import atexit
+            import weakref
+            _servers = weakref.WeakSet()
+            atexit.register(lambda: [s.close() for s in list(_servers)])
+        _servers.add(self)
+
+    def set_key(self, slot: int, sched):
+        s = np.ascontiguousarray(np.asarray(sched, dtype=SCHED_DTYPE).reshape(1))
+        _check(lib().aes_server_set_key(self.handle, slot, s.ctypes.data), "aes_server_set_key")
+
+    def submit(self, op: int, key_slot: int, iv, d_src, d_dst, length: int, callback=None):
+        """Posts a request; returns its ticket.  Raises AesError (status
+        AES_ERR_AGAIN when admission refuses).  callback(done_record) runs on
+        the library's completion thread."""
+        ivb = np.ascontiguousarray(np.frombuffer(bytes(iv), np.uint8)
+                                   if not isinstance(iv, np.ndarray) else iv, dtype=np.uint8)
+        t = ctypes.c_uint64()
+        cb = None
+        if callback is not None:
+            def _tramp(done_ptr, _user, _f=callback):
+                rec = np.frombuffer(ctypes.string_at(done_ptr, DONE_DTYPE.itemsize),
+                                    DONE_DTYPE)[0]
+                _f(rec)
+            cb = DONE_CB(_tramp)
+        st = lib().aes_server_submit(self.handle, op, key_slot, ivb.ctypes.data, _ptr(d_src),
+                                     _ptr(d_dst), length,
+                                     ctypes.cast(cb, ctypes.c_void_p) if cb else None, None,
+                                     ctypes.byref(t))
+        _check(st, "aes_server_submit")
+        if cb is not None:
+            self._cbs[t.value] = cb  # keep the trampoline alive
+        return t.value
+
+    def wait(self, ticket: int, timeout_s: float = 30.0):
+        out = np.zeros(1, DONE_DTYPE)
+        _check(lib().aes_server_wait(self.handle, ticket, int(timeout_s * 1e9), out.ctypes.data),
+               "aes_server_wait")
+        return out[0]
+
+    def poll(self, max_n: int = 1024) -> np.ndarray:
+        out = np.zeros(max_n, DONE_DTYPE)
+        n = ctypes.c_uint32()
+        _check(lib().aes_server_poll(self.handle, out.ctypes.data, max_n, ctypes.byref(n)),
+               "aes_server_poll")
+        return out[: n.value]
+
+    def replay(self, reqs: np.ndarray, arrival_s: np.ndarray, d_src_base, d_dst_base):
+        reqs = np.ascontiguousarray(reqs, dtype=REQ_DTYPE)
+        arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        out = np.zeros(reqs.size, DONE_DTYPE)
+        _check(lib().aes_server_replay(self.handle, reqs.ctypes.data, arr.ctypes.data, reqs.size,
+                                       _ptr(d_src_base), _ptr(d_dst_base), out.ctypes.data),
+               "aes_server_replay")
+        return out
+
+    def stats(self) -> dict:
+        out = np.zeros(len(STATS_NAMES), np.uint64)
+        _check(lib().aes_server_stats(self.handle, out.ctypes.data), "aes_server_stats")
+        return dict(zip(STATS_NAMES, (int(v) for v in out)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            st = lib().aes_server_destroy(self.handle)
+            self.handle = None
+            self._cbs.clear()
+            _check(st, "aes_server_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def __del__(self):
         try:

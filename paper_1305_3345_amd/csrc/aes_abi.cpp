@@ -27,6 +27,12 @@ int hip_fail(hipError_t e) {
     return AES_ERR_DEVICE;
 }
 
+}  // namespace
+
+int aesgpu::hip_fail_status(int hip_error) { return hip_fail((hipError_t)hip_error); }
+
+namespace {
+
 #define HIP_TRY(expr)                                                                              \
     do {                                                                                           \
         hipError_t e_ = (expr);                                                                    \
@@ -251,6 +257,15 @@ struct aes_plan {
     size_t n_dec = 0, n_ctr = 0, n_chain = 0;
     uint32_t tile_bytes = DEFAULT_TILE;
 };
+
+int aesgpu::ctx_info(const aes_ctx_t *ctx, CtxInfo *out) {
+    if (!ctx || !out)
+        return AES_ERR_ARG;
+    out->device = ctx->device;
+    out->n_cu = ctx->n_cu;
+    out->d_timg = ctx->d_timg;
+    return AES_OK;
+}
 
 namespace {
 
@@ -743,6 +758,22 @@ int aes_request_launch(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t 
     if (e)
         return hip_fail((hipError_t)e);
     return AES_OK;
+}
+
+int aes_request_launches(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+                         const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
+                         const aes_req_t *reqs, uint64_t n_reqs, void *stream) {
+    if (!ctx)
+        return AES_ERR_ARG;
+    int st = check_buffers(d_in, d_out, buf_bytes, n_reqs, d_scheds);
+    if (st)
+        return st;
+    if ((st = validate(reqs, n_reqs, n_scheds, buf_bytes)))
+        return st;
+    for (uint64_t i = 0; i < n_reqs && !st; i++)
+        st = aes_request_launch(ctx, d_scheds, n_scheds, d_in, d_out, buf_bytes, &reqs[i],
+                                stream);
+    return st;
 }
 
 // -------------------------------------------------------------- HIP graphs

@@ -1,424 +1,11 @@
-// aes_kernels.hip -- AES round kernels for CDNA4 (gfx950), table variant.
-//
-// The cipher is FIPS-197 in the round-table ("T-table") form: for encryption
-// one round of SubBytes, ShiftRows, MixColumns and AddRoundKey on column c is
-//   t_c = Te0[s_c.b0] ^ Te1[s_(c+1).b1] ^ Te2[s_(c+2).b2] ^ Te3[s_(c+3).b3] ^ rk_c,
-// with Te_k the S-box output times column k of the MixColumns circulant; the
-// equivalent inverse cipher (FIPS-197 5.3.5) has the same shape with Td_k,
-// columns c-k and the transformed round keys.  Modes are SP 800-38A: CTR
-// (6.5, 64-bit counter) and CBC decryption (6.2) run every block in
-// parallel; CBC encryption (6.2) is a serial chain per request.
-//
-// Layout in LDS (one workgroup per compute unit; tables are filled once per
-// workgroup and the grid walks over all work units):
-//   Each 1 KiB table is replicated 32 times so that lane l reads only bank
-//   l mod 32: entry x of table t lives at byte
-//     (t >> 1) << 16 | x << 8 | (t & 1) << 7 | (lane & 31) << 2.
-//   One v_perm_b32 builds that address from a state word and a per-lane
-//   constant (byte k of the state word into bits 8..15); the table parity is
-//   the ds_read immediate offset.  Four tables take 128 KiB.  Decryption adds
-//   the inverse S-box (Si4, byte repeated 4 times) at 128 KiB + x << 7 |
-//   (lane & 31) << 2, 32 KiB more, for the last round.
-//   Round keys are wave-uniform in the parallel kernels (one wave works one
-//   unit of one request) and live in SGPRs.
+// aes_kernels.hip -- batch kernels (tiles, chains, one fused launch, one
+// request per launch) over the round functions of aes_rounds.h.
 #include <hip/hip_runtime.h>
 
+#include "aes_rounds.h"
 #include "internal.h"
 
 namespace aesgpu {
-
-constexpr uint32_t LDS_ENC_WORDS = 32768;  // 128 KiB
-constexpr uint32_t LDS_DEC_WORDS = 40960;  // 160 KiB
-constexpr uint32_t SI_BASE = 0x20000u;     // byte address of Si4
-
-// ---------------------------------------------------------------- tables
-
-template <bool DEC>
-__device__ __forceinline__ void fill_tables(uint32_t *lds, const uint32_t *__restrict__ timg) {
-    const uint32_t base = DEC ? 1024u : 0u;
-    for (uint32_t i = threadIdx.x; i < 32768u; i += blockDim.x) {
-        const uint32_t tsel = (i >> 5) & 1u;
-        const uint32_t x = (i >> 6) & 255u;
-        const uint32_t region = i >> 14;
-        lds[i] = timg[base + (region * 2u + tsel) * 256u + x];
-    }
-    if (DEC) {
-        for (uint32_t i = threadIdx.x; i < 8192u; i += blockDim.x)
-            lds[32768u + i] = timg[2048u + (i >> 5)];
-    }
-}
-
-// Three-input XOR in one VALU op (v_bitop3_b32, truth table 0x96 = a ^ b ^ c).
-__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
-    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
-}
-
-__device__ __forceinline__ uint32_t lds_word(const uint32_t *lds, uint32_t byte_addr) {
-    return *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(lds) + byte_addr);
-}
-
-// Table T (0..3) looked up at byte K of v.  L is the lane constant of T's
-// 64 KiB region: byte 0 = (lane & 31) * 4, byte 2 = region.
-template <int K, int T>
-__device__ __forceinline__ uint32_t tlook(const uint32_t *lds, uint32_t v, uint32_t L0,
-                                          uint32_t L1) {
-    // v_perm_b32 selector: byte0 <- L.byte0, byte1 <- v.byte K, byte2 <- L.byte2, byte3 <- 0
-    const uint32_t a = __builtin_amdgcn_perm(v, T < 2 ? L0 : L1, 0x0C020400u | ((4u + K) << 8));
-    return lds_word(lds, a + ((T & 1) ? 128u : 0u));
-}
-
-// Inverse S-box byte K of v, read from Si4.  L2 = SI_BASE | (lane & 31) * 4.
-template <int K>
-__device__ __forceinline__ uint32_t silook(const uint32_t *lds, uint32_t v, uint32_t L2) {
-    const uint32_t x = (v >> (8 * K)) & 0xffu;
-    return lds_word(lds, (x << 7) | L2);
-}
-
-// Bytes 0,1 of a,b and bytes 2,3 of c,d: out byte r = (a,b,c,d)[r].byte r.
-__device__ __forceinline__ uint32_t pick_diag(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
-    const uint32_t lo = __builtin_amdgcn_perm(b, a, 0x0C0C0500u);
-    const uint32_t hi = __builtin_amdgcn_perm(d, c, 0x07020C0Cu);
-    return lo ^ hi;
-}
-
-// One full encryption round (SubBytes, ShiftRows, MixColumns, AddRoundKey).
-__device__ __forceinline__ void enc_round(const uint32_t *lds, uint32_t s[4],
-                                          const uint32_t *__restrict__ rk, uint32_t L0,
-                                          uint32_t L1) {
-    const uint32_t t0 = xor3(xor3(tlook<0, 0>(lds, s[0], L0, L1), tlook<1, 1>(lds, s[1], L0, L1),
-                                  tlook<2, 2>(lds, s[2], L0, L1)),
-                             tlook<3, 3>(lds, s[3], L0, L1), rk[0]);
-    const uint32_t t1 = xor3(xor3(tlook<0, 0>(lds, s[1], L0, L1), tlook<1, 1>(lds, s[2], L0, L1),
-                                  tlook<2, 2>(lds, s[3], L0, L1)),
-                             tlook<3, 3>(lds, s[0], L0, L1), rk[1]);
-    const uint32_t t2 = xor3(xor3(tlook<0, 0>(lds, s[2], L0, L1), tlook<1, 1>(lds, s[3], L0, L1),
-                                  tlook<2, 2>(lds, s[0], L0, L1)),
-                             tlook<3, 3>(lds, s[1], L0, L1), rk[2]);
-    const uint32_t t3 = xor3(xor3(tlook<0, 0>(lds, s[3], L0, L1), tlook<1, 1>(lds, s[0], L0, L1),
-                                  tlook<2, 2>(lds, s[1], L0, L1)),
-                             tlook<3, 3>(lds, s[2], L0, L1), rk[3]);
-    s[0] = t0;
-    s[1] = t1;
-    s[2] = t2;
-    s[3] = t3;
-}
-
-// Last encryption round (no MixColumns): Te_((r+3) mod 4) holds S(x) at byte r.
-// o_c = SubBytes/ShiftRows(s)_c ^ rk_c ^ x_c.
-__device__ __forceinline__ void enc_last(const uint32_t *lds, const uint32_t s[4],
-                                         const uint32_t *__restrict__ rk, uint32_t L0,
-                                         uint32_t L1, const uint32_t x[4], uint32_t o[4]) {
-#pragma unroll
-    for (int c = 0; c < 4; c++) {
-        const uint32_t a = tlook<0, 3>(lds, s[c], L0, L1);
-        const uint32_t b = tlook<1, 0>(lds, s[(c + 1) & 3], L0, L1);
-        const uint32_t d2 = tlook<2, 1>(lds, s[(c + 2) & 3], L0, L1);
-        const uint32_t d3 = tlook<3, 2>(lds, s[(c + 3) & 3], L0, L1);
-        o[c] = xor3(pick_diag(a, b, d2, d3), rk[c], x[c]);
-    }
-}
-
-// One round of the equivalent inverse cipher (InvSubBytes, InvShiftRows,
-// InvMixColumns, AddRoundKey with the transformed key): row r of column c
-// comes from column c - r.
-__device__ __forceinline__ void dec_round(const uint32_t *lds, uint32_t s[4],
-                                          const uint32_t *__restrict__ dk, uint32_t L0,
-                                          uint32_t L1) {
-    const uint32_t t0 = xor3(xor3(tlook<0, 0>(lds, s[0], L0, L1), tlook<1, 1>(lds, s[3], L0, L1),
-                                  tlook<2, 2>(lds, s[2], L0, L1)),
-                             tlook<3, 3>(lds, s[1], L0, L1), dk[0]);
-    const uint32_t t1 = xor3(xor3(tlook<0, 0>(lds, s[1], L0, L1), tlook<1, 1>(lds, s[0], L0, L1),
-                                  tlook<2, 2>(lds, s[3], L0, L1)),
-                             tlook<3, 3>(lds, s[2], L0, L1), dk[1]);
-    const uint32_t t2 = xor3(xor3(tlook<0, 0>(lds, s[2], L0, L1), tlook<1, 1>(lds, s[1], L0, L1),
-                                  tlook<2, 2>(lds, s[0], L0, L1)),
-                             tlook<3, 3>(lds, s[3], L0, L1), dk[2]);
-    const uint32_t t3 = xor3(xor3(tlook<0, 0>(lds, s[3], L0, L1), tlook<1, 1>(lds, s[2], L0, L1),
-                                  tlook<2, 2>(lds, s[1], L0, L1)),
-                             tlook<3, 3>(lds, s[0], L0, L1), dk[3]);
-    s[0] = t0;
-    s[1] = t1;
-    s[2] = t2;
-    s[3] = t3;
-}
-
-// Last inverse round: o_c byte r = InvS(s_(c-r).b_r) ^ dk ^ x.
-__device__ __forceinline__ void dec_last(const uint32_t *lds, const uint32_t s[4],
-                                         const uint32_t *__restrict__ dk, uint32_t L2,
-                                         const uint32_t x[4], uint32_t o[4]) {
-#pragma unroll
-    for (int c = 0; c < 4; c++) {
-        const uint32_t a = silook<0>(lds, s[c], L2);
-        const uint32_t b = silook<1>(lds, s[(c + 3) & 3], L2);
-        const uint32_t d2 = silook<2>(lds, s[(c + 2) & 3], L2);
-        const uint32_t d3 = silook<3>(lds, s[(c + 1) & 3], L2);
-        o[c] = xor3(pick_diag(a, b, d2, d3), dk[c], x[c]);
-    }
-}
-
-// ------------------------------------------------------------ block I/O
-
-// Loads block b of a unit of nbytes bytes; bytes past the end read as zero.
-__device__ __forceinline__ void load_block(const uint8_t *src, uint32_t b, uint32_t nbytes,
-                                           uint32_t x[4]) {
-    const uint32_t start = b << 4;
-    if (start + 16u <= nbytes) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(src + start);
-        x[0] = v.x;
-        x[1] = v.y;
-        x[2] = v.z;
-        x[3] = v.w;
-    } else {
-        x[0] = x[1] = x[2] = x[3] = 0u;
-        if (start < nbytes) {
-            for (uint32_t k = 0; k < nbytes - start; k++)
-                x[k >> 2] |= (uint32_t)src[start + k] << (8 * (k & 3));
-        }
-    }
-}
-
-__device__ __forceinline__ void store_block(uint8_t *dst, uint32_t b, uint32_t nbytes,
-                                            const uint32_t o[4]) {
-    const uint32_t start = b << 4;
-    if (start + 16u <= nbytes) {
-        *reinterpret_cast<uint4 *>(dst + start) = make_uint4(o[0], o[1], o[2], o[3]);
-    } else if (start < nbytes) {
-        for (uint32_t k = 0; k < nbytes - start; k++)
-            dst[start + k] = (uint8_t)(o[k >> 2] >> (8 * (k & 3)));
-    }
-}
-
-// -------------------------------------------------------------- CTR tiles
-
-// SP 800-38A 6.5: block b of the unit uses counter block nonce || BE64(ctr0 + b).
-template <int NB, int NR>
-__device__ __forceinline__ void ctr_unit(const uint32_t *lds, uint32_t L0, uint32_t L1,
-                                         uint32_t lane, const Unit &un,
-                                         const uint32_t *__restrict__ rk, const uint8_t *in,
-                                         uint8_t *out) {
-    const uint32_t nbytes = un.nbytes;
-    const uint32_t nblk = (nbytes + 15u) >> 4;
-    const uint64_t ctr0 = ((uint64_t)un.w[3] << 32) | un.w[2];
-    const uint32_t n0 = un.w[0] ^ rk[0];
-    const uint32_t n1 = un.w[1] ^ rk[1];
-    const uint8_t *src = in + un.off;
-    uint8_t *dst = out + un.off;
-    for (uint32_t base = 0; base < nblk; base += 64u * NB) {
-        uint32_t s[NB][4], x[NB][4];
-#pragma unroll
-        for (int i = 0; i < NB; i++) {
-            const uint32_t b = base + 64u * i + lane;
-            const uint64_t c = ctr0 + b;
-            s[i][0] = n0;
-            s[i][1] = n1;
-            s[i][2] = __builtin_bswap32((uint32_t)(c >> 32)) ^ rk[2];
-            s[i][3] = __builtin_bswap32((uint32_t)c) ^ rk[3];
-            load_block(src, b, nbytes, x[i]);
-        }
-#pragma unroll
-        for (int r = 1; r < NR; r++) {
-#pragma unroll
-            for (int i = 0; i < NB; i++)
-                enc_round(lds, s[i], rk + 4 * r, L0, L1);
-        }
-#pragma unroll
-        for (int i = 0; i < NB; i++) {
-            uint32_t o[4];
-            enc_last(lds, s[i], rk + 4 * NR, L0, L1, x[i], o);
-            store_block(dst, base + 64u * i + lane, nbytes, o);
-        }
-    }
-}
-
-// Key checks and round-count dispatch for one CTR unit (wave-uniform).
-template <int NB>
-__device__ __forceinline__ void run_ctr_unit(const uint32_t *lds, uint32_t L0, uint32_t L1,
-                                             uint32_t lane, const Unit &un,
-                                             const aes_schedule_t *__restrict__ sched,
-                                             uint32_t n_sched, const uint8_t *in, uint8_t *out) {
-    const uint32_t key = un.meta & META_KEY_MASK;
-    if (key >= n_sched)
-        return;
-    const aes_schedule_t *ks = sched + key;
-    const uint32_t nr = ks->nr;
-    if (nr == 10)
-        ctr_unit<NB, 10>(lds, L0, L1, lane, un, ks->ek, in, out);
-    else if (nr == 12)
-        ctr_unit<NB, 12>(lds, L0, L1, lane, un, ks->ek, in, out);
-    else if (nr == 14)
-        ctr_unit<NB, 14>(lds, L0, L1, lane, un, ks->ek, in, out);
-}
-
-// ------------------------------------------------------- CBC-decrypt tiles
-
-// DPP wave_shr:1 -- lane l receives lane l-1; lane 0 keeps `old`.
-__device__ __forceinline__ uint32_t shift_up(uint32_t old, uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, 0x138, 0xF, 0xF, false);
-}
-
-// SP 800-38A 6.2: P_j = D(C_j) ^ C_(j-1).  Lane l of step i decrypts block
-// 64i + l; its predecessor is lane l-1's ciphertext, and lane 0 takes lane 63
-// of the previous step (or the block before the unit).
-template <int NB, int NR>
-__device__ __forceinline__ void cbcdec_unit(const uint32_t *lds, uint32_t L0, uint32_t L1,
-                                            uint32_t L2, uint32_t lane, const Unit &un,
-                                            const uint4 *snap, const uint32_t *__restrict__ dk,
-                                            const uint8_t *in, uint8_t *out) {
-    const uint32_t nbytes = un.nbytes;
-    const uint32_t nblk = nbytes >> 4;
-    const uint8_t *src = in + un.off;
-    uint8_t *dst = out + un.off;
-    uint32_t carry[4];
-    if (un.meta & FLAG_PRED_IN) {
-        const uint4 p = snap ? *snap : *reinterpret_cast<const uint4 *>(src - 16);
-        carry[0] = p.x;
-        carry[1] = p.y;
-        carry[2] = p.z;
-        carry[3] = p.w;
-    } else {
-        carry[0] = un.w[0];
-        carry[1] = un.w[1];
-        carry[2] = un.w[2];
-        carry[3] = un.w[3];
-    }
-    for (uint32_t base = 0; base < nblk; base += 64u * NB) {
-        uint32_t c[NB][4], s[NB][4], pred[NB][4];
-#pragma unroll
-        for (int i = 0; i < NB; i++)
-            load_block(src, base + 64u * i + lane, nbytes, c[i]);
-#pragma unroll
-        for (int i = 0; i < NB; i++) {
-#pragma unroll
-            for (int w = 0; w < 4; w++) {
-                const uint32_t prev_last =
-                    i == 0 ? carry[w] : (uint32_t)__builtin_amdgcn_readlane((int)c[i - 1][w], 63);
-                pred[i][w] = shift_up(prev_last, c[i][w]);
-                s[i][w] = c[i][w] ^ dk[w];
-            }
-        }
-#pragma unroll
-        for (int w = 0; w < 4; w++)
-            carry[w] = (uint32_t)__builtin_amdgcn_readlane((int)c[NB - 1][w], 63);
-#pragma unroll
-        for (int r = 1; r < NR; r++) {
-#pragma unroll
-            for (int i = 0; i < NB; i++)
-                dec_round(lds, s[i], dk + 4 * r, L0, L1);
-        }
-#pragma unroll
-        for (int i = 0; i < NB; i++) {
-            uint32_t o[4];
-            dec_last(lds, s[i], dk + 4 * NR, L2, pred[i], o);
-            store_block(dst, base + 64u * i + lane, nbytes, o);
-        }
-    }
-}
-
-template <int NB>
-__device__ __forceinline__ void run_dec_unit(const uint32_t *lds, uint32_t L0, uint32_t L1,
-                                             uint32_t L2, uint32_t lane, const Unit &un,
-                                             const uint4 *snap,
-                                             const aes_schedule_t *__restrict__ sched,
-                                             uint32_t n_sched, const uint8_t *in, uint8_t *out) {
-    const uint32_t key = un.meta & META_KEY_MASK;
-    if (key >= n_sched)
-        return;
-    const aes_schedule_t *ks = sched + key;
-    const uint32_t nr = ks->nr;
-    if (nr == 10)
-        cbcdec_unit<NB, 10>(lds, L0, L1, L2, lane, un, snap, ks->dk, in, out);
-    else if (nr == 12)
-        cbcdec_unit<NB, 12>(lds, L0, L1, L2, lane, un, snap, ks->dk, in, out);
-    else if (nr == 14)
-        cbcdec_unit<NB, 14>(lds, L0, L1, L2, lane, un, snap, ks->dk, in, out);
-}
-
-// ------------------------------------------------------- CBC-encrypt chains
-
-// SP 800-38A 6.2: C_j = E(P_j ^ C_(j-1)); one chain per lane, strictly serial.
-// Round keys differ between lanes, so they live in VGPRs.
-template <int NR>
-__device__ __forceinline__ void chain_run(const uint32_t *lds, uint32_t L0, uint32_t L1,
-                                          const Unit &un, const uint32_t *ek, const uint8_t *in,
-                                          uint8_t *out) {
-    uint32_t rk[4 * (NR + 1)];
-#pragma unroll
-    for (int i = 0; i < NR + 1; i++) {
-        const uint4 v = reinterpret_cast<const uint4 *>(ek)[i];
-        rk[4 * i + 0] = v.x;
-        rk[4 * i + 1] = v.y;
-        rk[4 * i + 2] = v.z;
-        rk[4 * i + 3] = v.w;
-    }
-    uint32_t prev[4] = {un.w[0], un.w[1], un.w[2], un.w[3]};
-    const uint32_t nblk = un.nbytes >> 4;
-    const uint8_t *src = in + un.off;
-    uint8_t *dst = out + un.off;
-    constexpr uint32_t PF = 8;  // blocks fetched together: one 128-byte line per lane
-    for (uint32_t b = 0; b < nblk; b += PF) {
-        uint32_t x[PF][4];
-#pragma unroll
-        for (uint32_t j = 0; j < PF; j++) {
-            if (b + j < nblk) {
-                const uint4 v = *reinterpret_cast<const uint4 *>(src + ((b + j) << 4));
-                x[j][0] = v.x;
-                x[j][1] = v.y;
-                x[j][2] = v.z;
-                x[j][3] = v.w;
-            }
-        }
-#pragma unroll
-        for (uint32_t j = 0; j < PF; j++) {
-            if (b + j < nblk) {
-                uint32_t s[4];
-#pragma unroll
-                for (int w = 0; w < 4; w++)
-                    s[w] = x[j][w] ^ prev[w] ^ rk[w];
-#pragma unroll
-                for (int r = 1; r < NR; r++)
-                    enc_round(lds, s, rk + 4 * r, L0, L1);
-                const uint32_t zero[4] = {0u, 0u, 0u, 0u};
-                enc_last(lds, s, rk + 4 * NR, L0, L1, zero, prev);
-                *reinterpret_cast<uint4 *>(dst + ((b + j) << 4)) =
-                    make_uint4(prev[0], prev[1], prev[2], prev[3]);
-            }
-        }
-    }
-}
-
-// One chain per lane; lanes of one wave may have different keys and lengths.
-__device__ __forceinline__ void run_chain(const uint32_t *lds, uint32_t L0, uint32_t L1,
-                                          const Unit &un, const aes_schedule_t *__restrict__ sched,
-                                          uint32_t n_sched, const uint8_t *in, uint8_t *out) {
-    const uint32_t key = un.meta & META_KEY_MASK;
-    if (key >= n_sched)
-        return;
-    const aes_schedule_t *ks = sched + key;
-    const uint32_t nr = ks->nr;
-    if (nr == 10)
-        chain_run<10>(lds, L0, L1, un, ks->ek, in, out);
-    else if (nr == 12)
-        chain_run<12>(lds, L0, L1, un, ks->ek, in, out);
-    else if (nr == 14)
-        chain_run<14>(lds, L0, L1, un, ks->ek, in, out);
-}
-
-// Chains of a wave: `cl` active lanes per wave (spreading few chains over more
-// waves and compute units lowers nothing but the per-CU contention; each lane
-// is still one serial chain).  Wave e takes chains e*cl + lane, then strides.
-__device__ __forceinline__ void chain_loop(const uint32_t *lds, uint32_t L0, uint32_t L1,
-                                           uint32_t lane, uint32_t e, uint32_t n_waves,
-                                           uint32_t cl, const Unit *__restrict__ chains,
-                                           uint32_t n_chain,
-                                           const aes_schedule_t *__restrict__ sched,
-                                           uint32_t n_sched, const uint8_t *in, uint8_t *out) {
-    if (lane >= cl)
-        return;
-    for (uint64_t c = (uint64_t)e * cl + lane; c < n_chain; c += (uint64_t)n_waves * cl) {
-        const Unit un = chains[c];
-        run_chain(lds, L0, L1, un, sched, n_sched, in, out);
-    }
-}
 
 // ------------------------------------------------------------ tile kernels
 
@@ -566,7 +153,9 @@ __global__ __launch_bounds__(256) void k_request(aes_req_t r, uint32_t tile,
     const uint32_t L1 = L0 | 0x10000u;
     const uint32_t L2 = L0 | SI_BASE;
     if (!DEC && r.op == AES_OP_CBC_ENC) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // One serial chain: the first wave runs it on all lanes in lockstep
+        // (identical results and stores), keeping its control flow uniform.
+        if (blockIdx.x == 0 && threadIdx.x < 64u) {
             const Unit un = request_unit(r, 0, (uint32_t)r.length);
             run_chain(lds, L0, L1, un, sched, n_sched, in, out);
         }
@@ -703,18 +292,17 @@ int launch_request(const aes_req_t &r, uint32_t tile, const aes_schedule_t *d_sc
                    uint8_t *d_out, int n_cu, void *stream) {
     if (!r.length)
         return hipSuccess;
+    // One wave per workgroup and one tile per workgroup (up to one per
+    // compute unit): a request's tiles spread over as many compute units as
+    // it has tiles.
     const uint32_t n_units = (uint32_t)((r.length + tile - 1) / tile);
-    int grid = (int)((n_units + 3) / 4);
-    if (grid > n_cu)
-        grid = n_cu;
-    if (r.op == AES_OP_CBC_ENC)
-        grid = 1;
+    int grid = r.op == AES_OP_CBC_ENC ? 1 : (int)(n_units < (uint32_t)n_cu ? n_units : n_cu);
     if (r.op == AES_OP_CBC_DEC)
-        hipLaunchKernelGGL((k_request<true, 2>), dim3(grid), dim3(256), 0, (hipStream_t)stream, r,
+        hipLaunchKernelGGL((k_request<true, 2>), dim3(grid), dim3(64), 0, (hipStream_t)stream, r,
                            tile, d_sched, n_sched, d_timg, d_in, d_out);
     else
-        hipLaunchKernelGGL((k_request<false, 2>), dim3(grid), dim3(r.op == AES_OP_CBC_ENC ? 64 : 256),
-                           0, (hipStream_t)stream, r, tile, d_sched, n_sched, d_timg, d_in, d_out);
+        hipLaunchKernelGGL((k_request<false, 2>), dim3(grid), dim3(64), 0, (hipStream_t)stream, r,
+                           tile, d_sched, n_sched, d_timg, d_in, d_out);
     return hipGetLastError();
 }
 

@@ -1,0 +1,969 @@
+// aes_server.hip -- the serving form: a persistent kernel fed through a ring of
+// request descriptors in pinned host-mapped memory (the paper's Non-Stop
+// Kernel, section 3.1, with the request path of section 3.2), and the
+// per-request-launch engine it is compared with.
+//
+// Device side.  One wave of the grid (the dispatcher) polls the host ring with
+// system-scope acquire loads, 64 descriptors per round trip, cuts each
+// request into work units and publishes them to a device queue (one queue per
+// LDS table set: encryption tables for CTR tiles and CBC-encrypt chains,
+// decryption tables for CBC-decrypt tiles).  Every other wave claims units
+// from its workgroup's queue, runs them with the batch kernels' round code,
+// releases its output at system scope and decrements the request's unit
+// count; the wave that finishes the last unit writes the completion record
+// into host-mapped memory.  The dispatcher snapshots each CBC-decrypt tile's
+// predecessor block before publishing, so tiles run in any order and
+// in-place requests are safe.  The kernel ends when the host raises the stop
+// flag or no descriptor arrives for idle_timeout_ms; the host relaunches it
+// on demand.
+//
+// Host side.  aes_server_submit writes the descriptor fields, then its
+// sequence word with a release store; a completion thread watches the
+// completion records (or, in the per-launch engine, HIP events), applies
+// admission accounting, and runs callbacks or queues completions for
+// poll/wait.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "aes_rounds.h"
+#include "internal.h"
+
+namespace aesgpu {
+
+// Ring descriptor, 64 bytes, host-mapped.  seq = ticket + 1 once every other
+// field is written.
+struct ServeDesc {
+    uint64_t seq;
+    uint64_t src;
+    uint64_t dst;
+    uint32_t length;
+    uint32_t key_slot;
+    uint32_t op;
+    uint32_t reserved;
+    uint32_t iv[4];
+    uint64_t t_submit;
+};
+static_assert(sizeof(ServeDesc) == 64, "descriptor is 64 bytes");
+
+// Completion record, 32 bytes, host-mapped; seq = ticket + 1 written last.
+struct ServeDone {
+    uint64_t seq;
+    int32_t status;
+    uint32_t units;
+    uint64_t t_dispatch;
+    uint64_t t_done;
+};
+static_assert(sizeof(ServeDone) == 32, "completion is 32 bytes");
+
+// Work unit in a device queue, 64 bytes.
+struct ServeUnit {
+    Unit u;  // off = the tile's byte position inside the request
+    uint64_t src;
+    uint64_t dst;
+    uint64_t ticket;
+    uint32_t slot;
+    uint32_t reserved;
+};
+static_assert(sizeof(ServeUnit) == 64, "queue unit is 64 bytes");
+
+// Queue counters, each on its own 128-byte line.
+struct ServeQueue {
+    uint64_t head;  // next unit to claim
+    uint64_t pad0[15];
+    uint64_t tail;  // units published
+    uint64_t pad1[15];
+};
+
+// Host-mapped control block.
+struct ServeCtl {
+    uint32_t stop;  // host -> device
+    uint32_t pad0[31];
+    uint64_t consumed;   // device -> host: tickets taken from the ring
+    uint64_t heartbeat;  // device -> host: dispatcher polls
+    uint64_t pad1[14];
+};
+
+struct ServeArgs {
+    ServeDesc *ring;  // host-mapped (device address)
+    ServeDone *done;  // host-mapped (device address)
+    ServeCtl *ctl;    // host-mapped (device address)
+    ServeUnit *qunits[2];
+    ServeQueue *q;        // [2], device memory
+    uint32_t *closed;     // device memory
+    uint32_t *remaining;  // [ring_slots], device memory
+    const aes_schedule_t *keys;
+    const uint32_t *timg;
+    uint64_t start_ticket;
+    uint64_t idle_ticks;  // 100 MHz ticks
+    uint32_t ring_mask;
+    uint32_t qmask;
+    uint32_t n_keys;
+    uint32_t n_dec_wg;
+    uint32_t tile;
+    uint32_t max_bytes;
+};
+
+#define SYS __HIP_MEMORY_SCOPE_SYSTEM
+#define AGT __HIP_MEMORY_SCOPE_AGENT
+
+__device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
+
+__device__ __forceinline__ void complete(const ServeArgs &a, uint32_t slot, uint64_t ticket,
+                                         int32_t status) {
+    ServeDone *d = a.done + slot;
+    __hip_atomic_store(&d->status, status, __ATOMIC_RELAXED, SYS);
+    __hip_atomic_store(&d->t_done, now_ticks(), __ATOMIC_RELAXED, SYS);
+    __hip_atomic_store(&d->seq, ticket + 1, __ATOMIC_RELEASE, SYS);
+}
+
+// The dispatcher: one full wave.
+__device__ void dispatch_loop(const ServeArgs &a) {
+    const uint32_t lane = threadIdx.x & 63u;
+    uint64_t next = a.start_ticket;
+    uint64_t tail[2] = {__hip_atomic_load(&a.q[0].tail, __ATOMIC_RELAXED, AGT),
+                        __hip_atomic_load(&a.q[1].tail, __ATOMIC_RELAXED, AGT)};
+    uint64_t last_work = now_ticks();
+    uint32_t polls = 0;
+    for (;;) {
+        const uint64_t t = next + lane;
+        ServeDesc *d = a.ring + (t & a.ring_mask);
+        const uint64_t seq = __hip_atomic_load(&d->seq, __ATOMIC_ACQUIRE, SYS);
+        const uint64_t ready = __ballot(seq == t + 1);
+        const uint32_t n_ready = ~ready ? (uint32_t)__builtin_ctzll(~ready) : 64u;
+        if (n_ready == 0) {
+            if ((++polls & 63u) == 0 && lane == 0)
+                __hip_atomic_store(&a.ctl->heartbeat, (uint64_t)polls, __ATOMIC_RELAXED, SYS);
+            const uint32_t stop = __hip_atomic_load(&a.ctl->stop, __ATOMIC_RELAXED, SYS);
+            if (stop || now_ticks() - last_work > a.idle_ticks)
+                break;
+            __builtin_amdgcn_s_sleep(4);
+            continue;
+        }
+        // Lane i < n_ready reads descriptor next + i.
+        uint64_t src = 0, dst = 0, misc = 0, ivlo = 0, ivhi = 0;
+        uint32_t len = 0;
+        if (lane < n_ready) {
+            src = __hip_atomic_load(&d->src, __ATOMIC_RELAXED, SYS);
+            dst = __hip_atomic_load(&d->dst, __ATOMIC_RELAXED, SYS);
+            len = __hip_atomic_load(&d->length, __ATOMIC_RELAXED, SYS);
+            const uint32_t key = __hip_atomic_load(&d->key_slot, __ATOMIC_RELAXED, SYS);
+            const uint32_t op = __hip_atomic_load(&d->op, __ATOMIC_RELAXED, SYS);
+            misc = ((uint64_t)op << 32) | key;
+            ivlo = (uint64_t)__hip_atomic_load(&d->iv[0], __ATOMIC_RELAXED, SYS) |
+                   ((uint64_t)__hip_atomic_load(&d->iv[1], __ATOMIC_RELAXED, SYS) << 32);
+            ivhi = (uint64_t)__hip_atomic_load(&d->iv[2], __ATOMIC_RELAXED, SYS) |
+                   ((uint64_t)__hip_atomic_load(&d->iv[3], __ATOMIC_RELAXED, SYS) << 32);
+        }
+        for (uint32_t i = 0; i < n_ready; i++) {
+            const uint64_t ticket = next + i;
+            const uint32_t slot = (uint32_t)(ticket & a.ring_mask);
+            const uint64_t r_src = __shfl(src, (int)i);
+            const uint64_t r_dst = __shfl(dst, (int)i);
+            const uint32_t r_len = __shfl(len, (int)i);
+            const uint64_t r_misc = __shfl(misc, (int)i);
+            const uint64_t r_ivlo = __shfl(ivlo, (int)i);
+            const uint64_t r_ivhi = __shfl(ivhi, (int)i);
+            const uint32_t key = (uint32_t)r_misc;
+            const uint32_t op = (uint32_t)(r_misc >> 32);
+            const uint64_t t_disp = now_ticks();
+            if (lane == 0)
+                __hip_atomic_store(&a.done[slot].t_dispatch, t_disp, __ATOMIC_RELAXED, SYS);
+            const uint32_t k_units = op == AES_OP_CBC_ENC ? 1u : (r_len + a.tile - 1) / a.tile;
+            if (lane == 0)
+                __hip_atomic_store(&a.done[slot].units, k_units, __ATOMIC_RELAXED, SYS);
+            // The host validates every request; these checks keep a bad
+            // descriptor from reaching the kernels.
+            const bool ok = op <= AES_OP_CTR && key < a.n_keys && r_len > 0 &&
+                            r_len <= a.max_bytes && (op == AES_OP_CTR || (r_len & 15u) == 0) &&
+                            r_src && r_dst;
+            if (!ok) {
+                if (lane == 0)
+                    complete(a, slot, ticket, AES_ERR_ARG);
+                continue;
+            }
+            const int qi = op == AES_OP_CBC_DEC ? 1 : 0;
+            const uint32_t k = k_units;
+            // No wait for room: the host admits at most queue_units units
+            // per queue in flight, so published units are never overwritten
+            // before a worker has taken them.
+            if (lane == 0)
+                __hip_atomic_store(&a.remaining[slot], k, __ATOMIC_RELAXED, AGT);
+            const uint32_t w0 = (uint32_t)r_ivlo, w1 = (uint32_t)(r_ivlo >> 32);
+            const uint32_t w2 = (uint32_t)r_ivhi, w3 = (uint32_t)(r_ivhi >> 32);
+            for (uint32_t j = lane; j < k; j += 64u) {
+                ServeUnit su;
+                const uint32_t pos = j * a.tile;
+                su.u.off = pos;
+                su.u.nbytes = op == AES_OP_CBC_ENC ? r_len : min(a.tile, r_len - pos);
+                su.u.meta = key | (op << META_OP_SHIFT);
+                if (op == AES_OP_CTR) {
+                    const uint64_t c0 = ((uint64_t)__builtin_bswap32(w2) << 32) | __builtin_bswap32(w3);
+                    const uint64_t c = c0 + pos / 16u;
+                    su.u.w[0] = w0;
+                    su.u.w[1] = w1;
+                    su.u.w[2] = (uint32_t)c;
+                    su.u.w[3] = (uint32_t)(c >> 32);
+                } else if (j == 0) {
+                    su.u.w[0] = w0;
+                    su.u.w[1] = w1;
+                    su.u.w[2] = w2;
+                    su.u.w[3] = w3;
+                } else {
+                    // CBC decryption: the ciphertext block before this tile.
+                    const uint4 p =
+                        *reinterpret_cast<const uint4 *>((const uint8_t *)r_src + pos - 16);
+                    su.u.w[0] = p.x;
+                    su.u.w[1] = p.y;
+                    su.u.w[2] = p.z;
+                    su.u.w[3] = p.w;
+                }
+                su.src = r_src;
+                su.dst = r_dst;
+                su.ticket = ticket;
+                su.slot = slot;
+                su.reserved = 0;
+                a.qunits[qi][(tail[qi] + j) & a.qmask] = su;
+            }
+            tail[qi] += k;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (lane == 0)
+                __hip_atomic_store(&a.q[qi].tail, tail[qi], __ATOMIC_RELEASE, AGT);
+        }
+        next += n_ready;
+        if (lane == 0)
+            __hip_atomic_store(&a.ctl->consumed, next, __ATOMIC_RELAXED, SYS);
+        last_work = now_ticks();
+    }
+    if (lane == 0) {
+        __hip_atomic_store(&a.ctl->consumed, next, __ATOMIC_RELAXED, SYS);
+        __hip_atomic_store(a.closed, 1u, __ATOMIC_RELEASE, AGT);
+    }
+}
+
+// Wave-uniform read of a device-scope counter.
+__device__ __forceinline__ uint64_t load_u64_uniform(uint64_t *p) {
+    const uint64_t v = __hip_atomic_load(p, __ATOMIC_ACQUIRE, AGT);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Takes the next queue position (lane 0 adds 1 to head; every lane gets the
+// value) and waits, with the whole wave, until the dispatcher has published
+// it.  Returns false once the queue is closed and the position lies past the
+// last published unit.  All control flow here is wave-uniform: the unit
+// code that follows runs on all 64 lanes.
+__device__ __forceinline__ bool claim(const ServeArgs &a, int qi, uint64_t *idx) {
+    const uint32_t lane = threadIdx.x & 63u;
+    ServeQueue *q = a.q + qi;
+    uint64_t got = 0;
+    if (lane == 0)
+        got = __hip_atomic_fetch_add(&q->head, 1ull, __ATOMIC_ACQ_REL, AGT);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)got);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(got >> 32));
+    const uint64_t pos = ((uint64_t)hi << 32) | lo;
+    for (;;) {
+        if (pos < load_u64_uniform(&q->tail))
+            break;
+        const uint32_t closed =
+            __builtin_amdgcn_readfirstlane(__hip_atomic_load(a.closed, __ATOMIC_ACQUIRE, AGT));
+        if (closed) {
+            if (pos < load_u64_uniform(&q->tail))
+                break;
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(8);
+    }
+    *idx = pos;
+    return true;
+}
+
+template <bool DEC>
+__device__ void worker_loop(const ServeArgs &a, const uint32_t *lds) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t L0 = (lane & 31u) << 2;
+    const uint32_t L1 = L0 | 0x10000u;
+    const uint32_t L2 = L0 | SI_BASE;
+    const int qi = DEC ? 1 : 0;
+    uint64_t idx;
+    while (claim(a, qi, &idx)) {
+        // Input written by other agents must be re-read: acquire at system scope.
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+        const ServeUnit *p = a.qunits[qi] + (idx & a.qmask);
+        Unit un;
+        un.off = __hip_atomic_load(&p->u.off, __ATOMIC_RELAXED, AGT);
+        un.nbytes = __hip_atomic_load(&p->u.nbytes, __ATOMIC_RELAXED, AGT);
+        un.meta = __hip_atomic_load(&p->u.meta, __ATOMIC_RELAXED, AGT);
+        for (int w = 0; w < 4; w++)
+            un.w[w] = __hip_atomic_load(&p->u.w[w], __ATOMIC_RELAXED, AGT);
+        const uint8_t *src = (const uint8_t *)__hip_atomic_load(&p->src, __ATOMIC_RELAXED, AGT);
+        uint8_t *dst = (uint8_t *)__hip_atomic_load(&p->dst, __ATOMIC_RELAXED, AGT);
+        const uint64_t ticket = __hip_atomic_load(&p->ticket, __ATOMIC_RELAXED, AGT);
+        const uint32_t slot = __hip_atomic_load(&p->slot, __ATOMIC_RELAXED, AGT);
+        const uint32_t op = (un.meta >> META_OP_SHIFT) & 3u;
+        if (DEC) {
+            run_dec_unit<1>(lds, L0, L1, L2, lane, un, nullptr, a.keys, a.n_keys, src, dst);
+        } else if (op == AES_OP_CBC_ENC) {
+            // One chain: every lane runs it in lockstep (same result, same
+            // stores), which costs the time of one lane and keeps the wave's
+            // control flow uniform.
+            run_chain(lds, L0, L1, un, a.keys, a.n_keys, src, dst);
+        } else {
+            run_ctr_unit<1>(lds, L0, L1, lane, un, a.keys, a.n_keys, src, dst);
+        }
+        // Make this unit's output visible beyond the device, then count it.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+        uint32_t left = 0;
+        if (lane == 0)
+            left = __hip_atomic_fetch_sub(&a.remaining[slot], 1u, __ATOMIC_ACQ_REL, AGT);
+        left = __builtin_amdgcn_readfirstlane(left);
+        if (left == 1u && lane == 0)
+            complete(a, slot, ticket, AES_OK);
+    }
+}
+
+// Run before every launch of k_serve (same stream): reopens the queues and
+// drops positions taken by waves of the previous run that found no unit.
+__global__ void k_serve_reset(ServeQueue *q, uint32_t *closed) {
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < 2; i++)
+            q[i].head = q[i].tail;
+        *closed = 0u;
+    }
+}
+
+__global__ __launch_bounds__(512) void k_serve(ServeArgs a) {
+    __shared__ uint32_t lds[LDS_DEC_WORDS];
+    const bool dec = blockIdx.x < a.n_dec_wg;
+    if (dec)
+        fill_tables<true>(lds, a.timg);
+    else
+        fill_tables<false>(lds, a.timg);
+    __syncthreads();
+    if (blockIdx.x == gridDim.x - 1 && (threadIdx.x >> 6) == 0) {
+        dispatch_loop(a);
+        return;
+    }
+    if (dec)
+        worker_loop<true>(a, lds);
+    else
+        worker_loop<false>(a, lds);
+}
+
+}  // namespace aesgpu
+
+// ======================================================================= host
+
+using aesgpu::ServeArgs;
+using aesgpu::ServeCtl;
+using aesgpu::ServeDesc;
+using aesgpu::ServeDone;
+using aesgpu::ServeQueue;
+using aesgpu::ServeUnit;
+
+namespace {
+
+uint64_t host_ns() {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+inline void cpu_relax() { __builtin_ia32_pause(); }
+
+struct SlotInfo {
+    uint64_t ticket = 0;
+    uint64_t length = 0;
+    uint32_t units = 0;  // work units admitted to queue `queue` (persistent engine)
+    int queue = 0;
+    aes_done_cb cb = nullptr;
+    void *user = nullptr;
+    uint64_t t_submit = 0;
+    bool busy = false;
+    bool by_launch = false;  // completion comes from a HIP event
+};
+
+}  // namespace
+
+struct aes_server {
+    aes_ctx_t *ctx = nullptr;
+    aes_server_config_t cfg;
+    int device = 0;
+    uint32_t mask = 0;
+    uint32_t n_wg = 0, n_dec_wg = 0;
+    // host-mapped (host and device views)
+    ServeDesc *ring = nullptr, *ring_d = nullptr;
+    ServeDone *done = nullptr, *done_d = nullptr;
+    ServeCtl *ctl = nullptr, *ctl_d = nullptr;
+    // device memory
+    aes_schedule_t *keys_d = nullptr;
+    ServeUnit *qunits_d[2] = {nullptr, nullptr};
+    ServeQueue *q_d = nullptr;
+    uint32_t *closed_d = nullptr;
+    uint32_t *remaining_d = nullptr;
+    const uint32_t *timg_d = nullptr;
+    hipStream_t kstream = nullptr;     // the persistent kernel
+    hipStream_t fbstream = nullptr;    // requests that take a normal launch
+    std::vector<hipStream_t> streams;  // per-launch engine
+    std::vector<hipEvent_t> events;    // one per ring slot
+    bool running = false;
+    // bookkeeping (under mu)
+    std::mutex mu;
+    std::condition_variable cv;
+    uint64_t next_ticket = 0;
+    uint64_t inflight_bytes = 0;
+    uint32_t inflight = 0;
+    uint64_t inflight_units[2] = {0, 0};
+    std::vector<SlotInfo> slots;
+    std::vector<uint64_t> live;
+    std::unordered_map<uint64_t, aes_done_t> finished;
+    std::deque<uint64_t> finished_order;
+    aes_server_stats_t stats{};
+    std::thread poller;
+    std::atomic<bool> quit{false};
+};
+
+namespace {
+
+using aesgpu::hip_fail_status;
+
+// Launches the persistent kernel from the ring position the last one reached.
+int launch_persistent(aes_server *s) {
+    hipError_t e;
+    hipLaunchKernelGGL(aesgpu::k_serve_reset, dim3(1), dim3(64), 0, s->kstream, s->q_d,
+                       s->closed_d);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return hip_fail_status(e);
+    __atomic_store_n(&s->ctl->stop, 0u, __ATOMIC_RELEASE);
+    ServeArgs a;
+    a.ring = s->ring_d;
+    a.done = s->done_d;
+    a.ctl = s->ctl_d;
+    a.qunits[0] = s->qunits_d[0];
+    a.qunits[1] = s->qunits_d[1];
+    a.q = s->q_d;
+    a.closed = s->closed_d;
+    a.remaining = s->remaining_d;
+    a.keys = s->keys_d;
+    a.timg = s->timg_d;
+    a.start_ticket = __atomic_load_n(&s->ctl->consumed, __ATOMIC_ACQUIRE);
+    a.idle_ticks = (uint64_t)s->cfg.idle_timeout_ms * 100000ull;
+    a.ring_mask = s->mask;
+    a.qmask = s->cfg.queue_units - 1;
+    a.n_keys = s->cfg.key_slots;
+    a.n_dec_wg = s->n_dec_wg;
+    a.tile = 4096;
+    a.max_bytes = (uint32_t)s->cfg.max_request_bytes;
+    hipLaunchKernelGGL(aesgpu::k_serve, dim3(s->n_wg), dim3(512), 0, s->kstream, a);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return hip_fail_status(e);
+    s->running = true;
+    s->stats.kernel_launches++;
+    return AES_OK;
+}
+
+// Asks the persistent kernel to exit and waits for it (caller holds mu).
+int stop_persistent(aes_server *s) {
+    if (!s->running)
+        return AES_OK;
+    __atomic_store_n(&s->ctl->stop, 1u, __ATOMIC_RELEASE);
+    hipError_t e = hipStreamSynchronize(s->kstream);
+    s->running = false;
+    __atomic_store_n(&s->ctl->stop, 0u, __ATOMIC_RELEASE);
+    return e == hipSuccess ? AES_OK : hip_fail_status(e);
+}
+
+void finish_slot(aes_server *s, uint32_t slot, int32_t status, uint32_t units, uint64_t gd,
+                 uint64_t gt, std::vector<std::pair<SlotInfo, aes_done_t>> &cbs) {
+    SlotInfo &si = s->slots[slot];
+    aes_done_t d;
+    d.ticket = si.ticket;
+    d.status = status;
+    d.units = units;
+    d.t_submit_ns = si.t_submit;
+    d.t_done_ns = host_ns();
+    d.gpu_dispatch_ticks = gd;
+    d.gpu_done_ticks = gt;
+    s->inflight--;
+    s->inflight_bytes -= si.length;
+    s->inflight_units[si.queue] -= si.units;
+    s->stats.completed++;
+    if (si.cb) {
+        cbs.emplace_back(si, d);
+    } else {
+        s->finished[si.ticket] = d;
+        s->finished_order.push_back(si.ticket);
+    }
+    si.busy = false;
+}
+
+// The completion thread.
+void poll_loop(aes_server *s) {
+    std::vector<std::pair<SlotInfo, aes_done_t>> cbs;
+    uint64_t last_check = host_ns();
+    while (!s->quit.load(std::memory_order_acquire)) {
+        bool progressed = false;
+        bool busy;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (size_t i = 0; i < s->live.size();) {
+                const uint64_t t = s->live[i];
+                const uint32_t slot = (uint32_t)(t & s->mask);
+                SlotInfo &si = s->slots[slot];
+                bool fin = false;
+                int32_t st = AES_OK;
+                uint32_t units = 0;
+                uint64_t gd = 0, gt = 0;
+                if (si.by_launch) {
+                    const hipError_t e = hipEventQuery(s->events[slot]);
+                    if (e == hipSuccess) {
+                        fin = true;
+                    } else if (e != hipErrorNotReady) {
+                        fin = true;
+                        st = hip_fail_status(e);
+                    }
+                } else if (__atomic_load_n(&s->done[slot].seq, __ATOMIC_ACQUIRE) == t + 1) {
+                    fin = true;
+                    st = s->done[slot].status;
+                    units = s->done[slot].units;
+                    gd = s->done[slot].t_dispatch;
+                    gt = s->done[slot].t_done;
+                }
+                if (fin) {
+                    finish_slot(s, slot, st, units, gd, gt, cbs);
+                    s->live[i] = s->live.back();
+                    s->live.pop_back();
+                    progressed = true;
+                } else {
+                    i++;
+                }
+            }
+            busy = !s->live.empty();
+            // The persistent kernel may have exited on idle between a submit
+            // and its launch check: relaunch it while descriptors wait.
+            const uint64_t now = host_ns();
+            if (s->cfg.mode == AES_SERVE_PERSISTENT && s->running && busy && !progressed &&
+                now - last_check > 1000000ull) {
+                last_check = now;
+                if (hipStreamQuery(s->kstream) == hipSuccess) {
+                    s->running = false;
+                    if (__atomic_load_n(&s->ctl->consumed, __ATOMIC_ACQUIRE) < s->next_ticket)
+                        (void)launch_persistent(s);
+                }
+            }
+        }
+        if (progressed)
+            s->cv.notify_all();
+        for (auto &c : cbs)
+            c.first.cb(&c.second, c.first.user);
+        cbs.clear();
+        if (!progressed) {
+            if (busy) {
+                for (int k = 0; k < 16; k++)
+                    cpu_relax();
+            } else {
+                std::this_thread::sleep_for(std::chrono::microseconds(20));
+            }
+        }
+    }
+}
+
+int check_request(aes_server *s, uint32_t op, uint32_t key_slot, const uint8_t *iv,
+                  const uint8_t *src, uint8_t *dst, uint64_t length) {
+    if (op > AES_OP_CTR || !iv || !src || !dst || !length)
+        return AES_ERR_ARG;
+    if (length > (1ull << 32) - 16 || (op != AES_OP_CTR && (length & 15)))
+        return AES_ERR_LENGTH;
+    if (key_slot >= s->cfg.key_slots)
+        return AES_ERR_RANGE;
+    if (src != dst) {
+        const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
+        if (a < b + length && b < a + length)
+            return AES_ERR_OVERLAP;
+    }
+    return AES_OK;
+}
+
+// Posts one request (caller holds mu).
+int submit_locked(aes_server *s, uint32_t op, uint32_t key_slot, const uint8_t *iv,
+                  const uint8_t *src, uint8_t *dst, uint64_t length, aes_done_cb cb, void *user,
+                  uint64_t t_submit, uint64_t *ticket_out) {
+    const uint64_t ticket = s->next_ticket;
+    const uint32_t slot = (uint32_t)(ticket & s->mask);
+    if (s->slots[slot].busy ||
+        (s->inflight && s->inflight_bytes + length > s->cfg.hbm_cap_bytes)) {
+        s->stats.rejected_again++;
+        return AES_ERR_AGAIN;
+    }
+    const bool by_launch = s->cfg.mode == AES_SERVE_PER_LAUNCH ||
+                           length > s->cfg.max_request_bytes;
+    // Units this request adds to its device queue; the queue never holds
+    // more than queue_units unconsumed units (see the dispatcher).
+    const int queue = op == AES_OP_CBC_DEC ? 1 : 0;
+    const uint32_t units =
+        by_launch ? 0u : (op == AES_OP_CBC_ENC ? 1u : (uint32_t)((length + 4095) / 4096));
+    if (s->inflight_units[queue] + units > s->cfg.queue_units) {
+        s->stats.rejected_again++;
+        return AES_ERR_AGAIN;
+    }
+    if (by_launch) {
+        aes_req_t r;
+        r.offset = 0;
+        r.length = length;
+        r.key_idx = key_slot;
+        r.op = op;
+        memcpy(r.iv, iv, 16);
+        hipStream_t st = s->cfg.mode == AES_SERVE_PER_LAUNCH
+                             ? s->streams[ticket % s->streams.size()]
+                             : s->fbstream;
+        int rc = aes_request_launch(s->ctx, s->keys_d, s->cfg.key_slots, src, dst, length, &r, st);
+        if (rc)
+            return rc;
+        hipError_t e = hipEventRecord(s->events[slot], st);
+        if (e != hipSuccess)
+            return hip_fail_status(e);
+        if (s->cfg.mode == AES_SERVE_PERSISTENT)
+            s->stats.fallbacks++;
+    } else {
+        ServeDesc *d = s->ring + slot;
+        d->src = (uint64_t)(uintptr_t)src;
+        d->dst = (uint64_t)(uintptr_t)dst;
+        d->length = (uint32_t)length;
+        d->key_slot = key_slot;
+        d->op = op;
+        d->reserved = 0;
+        memcpy(d->iv, iv, 16);
+        d->t_submit = t_submit;
+        __atomic_store_n(&d->seq, ticket + 1, __ATOMIC_RELEASE);
+        if (!s->running) {
+            int rc = launch_persistent(s);
+            if (rc)
+                return rc;
+        }
+    }
+    SlotInfo &si = s->slots[slot];
+    si.ticket = ticket;
+    si.length = length;
+    si.cb = cb;
+    si.user = user;
+    si.t_submit = t_submit;
+    si.busy = true;
+    si.by_launch = by_launch;
+    si.units = units;
+    si.queue = queue;
+    s->next_ticket++;
+    s->inflight++;
+    s->inflight_bytes += length;
+    s->inflight_units[queue] += units;
+    s->live.push_back(ticket);
+    s->stats.submitted++;
+    if (ticket_out)
+        *ticket_out = ticket;
+    return AES_OK;
+}
+
+void free_server(aes_server *s) {
+    if (s->poller.joinable()) {
+        s->quit.store(true, std::memory_order_release);
+        s->poller.join();
+    }
+    (void)hipSetDevice(s->device);
+    for (hipEvent_t e : s->events)
+        (void)hipEventDestroy(e);
+    for (hipStream_t st : s->streams)
+        (void)hipStreamDestroy(st);
+    if (s->kstream)
+        (void)hipStreamDestroy(s->kstream);
+    if (s->fbstream)
+        (void)hipStreamDestroy(s->fbstream);
+    if (s->ring)
+        (void)hipHostFree(s->ring);
+    if (s->done)
+        (void)hipHostFree(s->done);
+    if (s->ctl)
+        (void)hipHostFree(s->ctl);
+    for (void *p : {(void *)s->keys_d, (void *)s->qunits_d[0], (void *)s->qunits_d[1],
+                    (void *)s->q_d, (void *)s->closed_d, (void *)s->remaining_d})
+        if (p)
+            (void)hipFree(p);
+    delete s;
+}
+
+bool pow2(uint32_t v) { return v && !(v & (v - 1)); }
+
+}  // namespace
+
+extern "C" {
+
+int aes_server_create(aes_ctx_t *ctx, const aes_server_config_t *cfg_in, aes_server_t **out) {
+    if (!ctx || !out)
+        return AES_ERR_ARG;
+    *out = nullptr;
+    aes_server_config_t cfg;
+    memset(&cfg, 0, sizeof(cfg));
+    if (cfg_in)
+        cfg = *cfg_in;
+    if (!cfg.ring_slots)
+        cfg.ring_slots = 4096;
+    if (!cfg.key_slots)
+        cfg.key_slots = 256;
+    if (!cfg.n_streams)
+        cfg.n_streams = 8;
+    if (!cfg.queue_units)
+        cfg.queue_units = 65536;
+    if (!cfg.idle_timeout_ms)
+        cfg.idle_timeout_ms = 1000;
+    if (!cfg.hbm_cap_bytes)
+        cfg.hbm_cap_bytes = 256ull << 20;
+    if (!cfg.max_request_bytes)
+        cfg.max_request_bytes = 4ull << 20;
+    if (cfg.mode > AES_SERVE_PER_LAUNCH || !pow2(cfg.ring_slots) || cfg.ring_slots < 64 ||
+        cfg.ring_slots > 65536 || cfg.key_slots > 65536 || !pow2(cfg.queue_units) ||
+        cfg.queue_units < 1024 || cfg.n_streams > 64 ||
+        cfg.max_request_bytes > (uint64_t)(cfg.queue_units) * 4096 ||
+        cfg.max_request_bytes > (1ull << 32) - 16)
+        return AES_ERR_ARG;
+    aesgpu::CtxInfo ci;
+    int st = aesgpu::ctx_info(ctx, &ci);
+    if (st)
+        return st;
+    if (ci.device == AES_DEVICE_NONE)
+        return AES_ERR_DEVICE;
+    aes_server *s = new (std::nothrow) aes_server();
+    if (!s)
+        return AES_ERR_NOMEM;
+    s->ctx = ctx;
+    s->cfg = cfg;
+    s->device = ci.device;
+    s->mask = cfg.ring_slots - 1;
+    s->timg_d = ci.d_timg;
+    int n_wg = cfg.n_workgroups ? (int)cfg.n_workgroups : ci.n_cu - 16;
+    if (n_wg < 2)
+        n_wg = 2;
+    int n_dec = cfg.dec_workgroups ? (int)cfg.dec_workgroups : n_wg / 2;
+    if (n_dec < 1 || n_dec > n_wg - 1) {
+        delete s;
+        return AES_ERR_ARG;
+    }
+    s->n_wg = (uint32_t)n_wg;
+    s->n_dec_wg = (uint32_t)n_dec;
+    hipError_t e;
+#define SRV_TRY(expr)                                                                              \
+    do {                                                                                           \
+        if ((e = (expr)) != hipSuccess) {                                                          \
+            free_server(s);                                                                        \
+            return hip_fail_status(e);                                                             \
+        }                                                                                          \
+    } while (0)
+    SRV_TRY(hipSetDevice(s->device));
+    const unsigned hflags = hipHostMallocMapped | hipHostMallocCoherent;
+    SRV_TRY(hipHostMalloc((void **)&s->ring, sizeof(ServeDesc) * cfg.ring_slots, hflags));
+    SRV_TRY(hipHostMalloc((void **)&s->done, sizeof(ServeDone) * cfg.ring_slots, hflags));
+    SRV_TRY(hipHostMalloc((void **)&s->ctl, sizeof(ServeCtl), hflags));
+    memset(s->ring, 0, sizeof(ServeDesc) * cfg.ring_slots);
+    memset(s->done, 0, sizeof(ServeDone) * cfg.ring_slots);
+    memset(s->ctl, 0, sizeof(ServeCtl));
+    SRV_TRY(hipHostGetDevicePointer((void **)&s->ring_d, s->ring, 0));
+    SRV_TRY(hipHostGetDevicePointer((void **)&s->done_d, s->done, 0));
+    SRV_TRY(hipHostGetDevicePointer((void **)&s->ctl_d, s->ctl, 0));
+    SRV_TRY(hipMalloc((void **)&s->keys_d, sizeof(aes_schedule_t) * cfg.key_slots));
+    SRV_TRY(hipMemset(s->keys_d, 0, sizeof(aes_schedule_t) * cfg.key_slots));
+    if (cfg.mode == AES_SERVE_PERSISTENT) {
+        for (int i = 0; i < 2; i++)
+            SRV_TRY(hipMalloc((void **)&s->qunits_d[i], sizeof(ServeUnit) * cfg.queue_units));
+        SRV_TRY(hipMalloc((void **)&s->q_d, sizeof(ServeQueue) * 2));
+        SRV_TRY(hipMemset(s->q_d, 0, sizeof(ServeQueue) * 2));
+        SRV_TRY(hipMalloc((void **)&s->closed_d, sizeof(uint32_t)));
+        SRV_TRY(hipMalloc((void **)&s->remaining_d, sizeof(uint32_t) * cfg.ring_slots));
+        SRV_TRY(hipMemset(s->remaining_d, 0, sizeof(uint32_t) * cfg.ring_slots));
+        SRV_TRY(hipStreamCreateWithFlags(&s->kstream, hipStreamNonBlocking));
+        SRV_TRY(hipStreamCreateWithFlags(&s->fbstream, hipStreamNonBlocking));
+    } else {
+        s->streams.resize(cfg.n_streams, nullptr);
+        for (auto &st2 : s->streams)
+            SRV_TRY(hipStreamCreateWithFlags(&st2, hipStreamNonBlocking));
+    }
+    s->events.resize(cfg.ring_slots, nullptr);
+    for (auto &ev : s->events)
+        SRV_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+#undef SRV_TRY
+    s->slots.resize(cfg.ring_slots);
+    s->live.reserve(cfg.ring_slots);
+    try {
+        s->poller = std::thread(poll_loop, s);
+    } catch (...) {
+        free_server(s);
+        return AES_ERR_NOMEM;
+    }
+    *out = s;
+    return AES_OK;
+}
+
+int aes_server_set_key(aes_server_t *s, uint32_t slot, const aes_schedule_t *host_sched) {
+    if (!s || !host_sched)
+        return AES_ERR_ARG;
+    if (slot >= s->cfg.key_slots)
+        return AES_ERR_RANGE;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->inflight)
+        return AES_ERR_STATE;
+    hipError_t e = hipSetDevice(s->device);
+    if (e != hipSuccess)
+        return hip_fail_status(e);
+    int st = stop_persistent(s);
+    if (st)
+        return st;
+    if ((e = hipMemcpy(s->keys_d + slot, host_sched, sizeof(aes_schedule_t),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail_status(e);
+    return AES_OK;
+}
+
+int aes_server_submit(aes_server_t *s, uint32_t op, uint32_t key_slot, const uint8_t iv[16],
+                      const uint8_t *d_src, uint8_t *d_dst, uint64_t length, aes_done_cb cb,
+                      void *user, uint64_t *ticket) {
+    if (!s)
+        return AES_ERR_ARG;
+    int st = check_request(s, op, key_slot, iv, d_src, d_dst, length);
+    if (st)
+        return st;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (hipSetDevice(s->device) != hipSuccess)
+        return AES_ERR_DEVICE;
+    return submit_locked(s, op, key_slot, iv, d_src, d_dst, length, cb, user, host_ns(), ticket);
+}
+
+int aes_server_poll(aes_server_t *s, aes_done_t *out, uint32_t max, uint32_t *n_out) {
+    if (!s || !n_out || (max && !out))
+        return AES_ERR_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    uint32_t n = 0;
+    while (n < max && !s->finished_order.empty()) {
+        const uint64_t t = s->finished_order.front();
+        s->finished_order.pop_front();
+        auto it = s->finished.find(t);
+        if (it == s->finished.end())
+            continue;  // already taken by aes_server_wait
+        out[n++] = it->second;
+        s->finished.erase(it);
+    }
+    *n_out = n;
+    return AES_OK;
+}
+
+int aes_server_wait(aes_server_t *s, uint64_t ticket, uint64_t timeout_ns, aes_done_t *out) {
+    if (!s)
+        return AES_ERR_ARG;
+    std::unique_lock<std::mutex> lk(s->mu);
+    const auto deadline = std::chrono::steady_clock::now() + std::chrono::nanoseconds(timeout_ns);
+    for (;;) {
+        auto it = s->finished.find(ticket);
+        if (it != s->finished.end()) {
+            if (out)
+                *out = it->second;
+            s->finished.erase(it);
+            return AES_OK;
+        }
+        const SlotInfo &si = s->slots[ticket & s->mask];
+        if (ticket >= s->next_ticket || !si.busy || si.ticket != ticket || si.cb)
+            return AES_ERR_ARG;
+        if (s->cv.wait_until(lk, deadline) == std::cv_status::timeout &&
+            s->finished.find(ticket) == s->finished.end())
+            return AES_ERR_TIMEOUT;
+    }
+}
+
+int aes_server_replay(aes_server_t *s, const aes_req_t *reqs, const double *arrival_s, uint64_t n,
+                      const uint8_t *d_src_base, uint8_t *d_dst_base, aes_done_t *out) {
+    if (!s || (n && (!reqs || !arrival_s || !out || !d_src_base || !d_dst_base)))
+        return AES_ERR_ARG;
+    for (uint64_t i = 0; i < n; i++) {
+        int st = check_request(s, reqs[i].op, reqs[i].key_idx, reqs[i].iv,
+                               d_src_base + reqs[i].offset, d_dst_base + reqs[i].offset,
+                               reqs[i].length);
+        if (st)
+            return st;
+    }
+    std::vector<uint64_t> tickets(n, ~0ull);
+    const uint64_t t0 = host_ns() + 1000000ull;
+    for (uint64_t i = 0; i < n; i++) {
+        const uint64_t target = t0 + (uint64_t)(arrival_s[i] * 1e9);
+        while (host_ns() < target)
+            cpu_relax();
+        for (;;) {
+            int st;
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                st = submit_locked(s, reqs[i].op, reqs[i].key_idx, reqs[i].iv,
+                                   d_src_base + reqs[i].offset, d_dst_base + reqs[i].offset,
+                                   reqs[i].length, nullptr, nullptr, target, &tickets[i]);
+            }
+            if (st == AES_OK)
+                break;
+            if (st != AES_ERR_AGAIN) {
+                memset(&out[i], 0, sizeof(out[i]));
+                out[i].status = st;
+                out[i].ticket = ~0ull;
+                break;
+            }
+            cpu_relax();
+        }
+    }
+    int rc = AES_OK;
+    for (uint64_t i = 0; i < n; i++) {
+        if (tickets[i] == ~0ull)
+            continue;
+        int st = aes_server_wait(s, tickets[i], 60ull * 1000000000ull, &out[i]);
+        if (st && !rc)
+            rc = st;
+    }
+    return rc;
+}
+
+int aes_server_stats(aes_server_t *s, aes_server_stats_t *out) {
+    if (!s || !out)
+        return AES_ERR_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->stats;
+    out->in_flight = s->inflight;
+    out->in_flight_bytes = s->inflight_bytes;
+    return AES_OK;
+}
+
+int aes_server_destroy(aes_server_t *s) {
+    if (!s)
+        return AES_OK;
+    int rc = AES_OK;
+    {
+        std::unique_lock<std::mutex> lk(s->mu);
+        const auto deadline = std::chrono::steady_clock::now() + std::chrono::seconds(10);
+        while (s->inflight) {
+            if (s->cv.wait_until(lk, deadline) == std::cv_status::timeout && s->inflight) {
+                rc = AES_ERR_TIMEOUT;
+                break;
+            }
+        }
+        (void)hipSetDevice(s->device);
+        int st = stop_persistent(s);
+        if (st && !rc)
+            rc = st;
+        if (s->fbstream)
+            (void)hipStreamSynchronize(s->fbstream);
+        for (hipStream_t st2 : s->streams)
+            (void)hipStreamSynchronize(st2);
+    }
+    free_server(s);
+    return rc;
+}
+
+}  // extern "C"

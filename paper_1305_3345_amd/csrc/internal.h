@@ -87,6 +87,18 @@ int launch_request(const aes_req_t &r, uint32_t tile, const aes_schedule_t *d_sc
 int launch_snapshot_preds(const Unit *d_units, uint32_t n_units, const uint8_t *d_in,
                           void *d_preds, void *stream);
 
+// Records a failing hipError_t for aes_last_hip_error and returns
+// AES_ERR_DEVICE (aes_abi.cpp).
+int hip_fail_status(int hip_error);
+
+// What the server needs to know about a context.
+struct CtxInfo {
+    int device;
+    int n_cu;
+    const uint32_t *d_timg;
+};
+int ctx_info(const aes_ctx_t *ctx, CtxInfo *out);
+
 // Host table generation (tables.cpp).
 void make_table_image(uint32_t img[TIMG_WORDS]);
 int expand_key(const uint8_t *key, uint32_t key_bits, aes_schedule_t *out);

@@ -1,0 +1,271 @@
+"""GPU tests of the serving form (persistent kernel and per-request-launch
+engines): every request's bytes must equal the oracle's and be identical
+alone and in the mix (tolerance 0); admission, fallback, idle exit and
+relaunch, errors, callbacks and trace replay.
+
+While a persistent kernel runs, tests synchronise only torch's current
+stream (a device-wide synchronise would wait for the persistent kernel)."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import gen, workloads
+from tests.gpu_util import ag, first_mismatch
+
+pytestmark = pytest.mark.gpu
+
+ENGINES = [0, 1]  # AES_SERVE_PERSISTENT, AES_SERVE_PER_LAUNCH
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    print("\n[gpu] context for serving tests", flush=True)
+    c = ag().Context(0)
+    yield c
+    c.close()
+
+
+def sync():
+    torch.cuda.current_stream().synchronize()
+
+
+def make_trace(n, seed=0, n_keys=8, sizes=(4, 8, 16, 32, 64), ctr_share=True):
+    """n requests over one staged buffer: sizes in KiB, ops CBC-enc/dec (and
+    CTR with ragged lengths), key slots 0..n_keys-1 with 128/256-bit keys."""
+    r = np.random.default_rng(seed)
+    kib = r.choice(np.array(sizes), n)
+    reqs = np.zeros(n, workloads.REQ_DTYPE)
+    reqs["length"] = kib * 1024
+    ops = r.integers(0, 3 if ctr_share else 2, n)
+    reqs["op"] = ops
+    ctr = reqs["op"] == workloads.OP_CTR
+    reqs["length"][ctr] -= r.integers(0, 16, ctr.sum()).astype(np.uint64)
+    reqs["offset"][1:] = np.cumsum((reqs["length"] + 15) // 16 * 16 + 64)[:-1]
+    reqs["key_idx"] = r.integers(0, n_keys, n)
+    reqs["iv"] = gen.bytes_(seed, gen.STREAM_IVS, 16 * n).reshape(n, 16)
+    keys, kb = workloads.make_keys(seed, n_keys, [128, 256] * (n_keys // 2))
+    buf = int(reqs["offset"][-1] + reqs["length"][-1] + 64)
+    return workloads.Workload("serve", reqs, keys, kb, buf, seed)
+
+
+def server(ctx, wl, **cfg):
+    a = ag()
+    s = a.Server(ctx, key_slots=wl.keys.shape[0], **cfg)
+    for i, sch in enumerate(a.expand_keys(wl.keys, wl.key_bits)):
+        s.set_key(i, sch)
+    return s
+
+
+def oracle_request(wl, r, src):
+    kb = int(wl.key_bits[r["key_idx"]])
+    return oracle.mode(int(r["op"]), wl.keys[r["key_idx"]][: kb // 8], kb, r["iv"], src)
+
+
+def submit_retry(s, r, d_src, d_dst):
+    a = ag()
+    while True:
+        try:
+            return s.submit(int(r["op"]), int(r["key_idx"]), r["iv"], d_src, d_dst,
+                            int(r["length"]))
+        except a.AesError as e:
+            if e.status != a.AES_ERR_AGAIN:
+                raise
+            time.sleep(20e-6)
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_alone_vs_mix(ctx, engine):
+    print(f"[gpu] serving alone vs mix, engine={engine}", flush=True)
+    wl = make_trace(120)
+    inp = wl.data()
+    d_in = torch.from_numpy(inp).cuda()
+    sync()
+    base = d_in.data_ptr()
+    outs = {}
+    with server(ctx, wl, mode=engine) as s:
+        for form in ("alone", "mix"):
+            d_out = torch.from_numpy(workloads.sentinel(inp.size)).cuda()
+            sync()
+            ob = d_out.data_ptr()
+            if form == "alone":
+                for r in wl.reqs:
+                    t = submit_retry(s, r, base + int(r["offset"]), ob + int(r["offset"]))
+                    assert s.wait(t)["status"] == 0
+            else:
+                tickets = [submit_retry(s, r, base + int(r["offset"]), ob + int(r["offset"]))
+                           for r in wl.reqs]
+                for t in tickets:
+                    assert s.wait(t)["status"] == 0
+            outs[form] = d_out.cpu().numpy()
+        st = s.stats()
+        assert st["completed"] == 2 * wl.reqs.size and st["in_flight"] == 0
+    msg = first_mismatch(outs["alone"], outs["mix"])
+    assert msg is None, f"alone vs mix: {msg}"
+    for r in wl.reqs:
+        o, n = int(r["offset"]), int(r["length"])
+        want = oracle_request(wl, r, inp[o:o + n])
+        msg = first_mismatch(outs["mix"][o:o + n], want)
+        assert msg is None, f"request at {o} op {int(r['op'])}: {msg}"
+    sent = workloads.sentinel(inp.size)
+    touched = np.zeros(inp.size, bool)
+    for r in wl.reqs:
+        touched[int(r["offset"]):int(r["offset"] + r["length"])] = True
+    assert np.array_equal(outs["mix"][~touched], sent[~touched])
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_in_place(ctx, engine):
+    print(f"[gpu] serving in place, engine={engine}", flush=True)
+    wl = make_trace(40, seed=3, sizes=(16, 64))
+    inp = wl.data()
+    d = torch.from_numpy(inp.copy()).cuda()
+    sync()
+    with server(ctx, wl, mode=engine) as s:
+        ts = [submit_retry(s, r, d.data_ptr() + int(r["offset"]), d.data_ptr() + int(r["offset"]))
+              for r in wl.reqs]
+        for t in ts:
+            assert s.wait(t)["status"] == 0
+        got = d.cpu().numpy()
+    for r in wl.reqs:
+        o, n = int(r["offset"]), int(r["length"])
+        assert first_mismatch(got[o:o + n], oracle_request(wl, r, inp[o:o + n])) is None
+
+
+def test_admission_backpressure(ctx):
+    print("[gpu] admission and backpressure", flush=True)
+    a = ag()
+    wl = make_trace(300, seed=5, sizes=(64,), ctr_share=False)
+    inp = wl.data()
+    d_in = torch.from_numpy(inp).cuda()
+    d_out = torch.empty_like(d_in)
+    sync()
+    with server(ctx, wl, ring_slots=64, hbm_cap_bytes=1 << 20) as s:
+        tickets, again = [], 0
+        for r in wl.reqs:
+            while True:
+                try:
+                    tickets.append(s.submit(int(r["op"]), int(r["key_idx"]), r["iv"],
+                                            d_in.data_ptr() + int(r["offset"]),
+                                            d_out.data_ptr() + int(r["offset"]), int(r["length"])))
+                    break
+                except a.AesError as e:
+                    assert e.status == a.AES_ERR_AGAIN
+                    again += 1
+                    st = s.stats()
+                    assert st["in_flight"] <= 64 and st["in_flight_bytes"] <= 1 << 20
+                    time.sleep(50e-6)
+        for t in tickets:
+            assert s.wait(t)["status"] == 0
+        assert again > 0, "the cap should have refused some submits"
+        got = d_out.cpu().numpy()
+    for r in wl.reqs[::7]:
+        o, n = int(r["offset"]), int(r["length"])
+        assert first_mismatch(got[o:o + n], oracle_request(wl, r, inp[o:o + n])) is None
+
+
+def test_oversize_request_takes_a_normal_launch(ctx):
+    print("[gpu] oversize fallback", flush=True)
+    wl = make_trace(6, seed=7, sizes=(1024,))
+    inp = wl.data()
+    d_in = torch.from_numpy(inp).cuda()
+    d_out = torch.empty_like(d_in)
+    sync()
+    with server(ctx, wl, max_request_bytes=256 << 10) as s:
+        ts = [submit_retry(s, r, d_in.data_ptr() + int(r["offset"]),
+                           d_out.data_ptr() + int(r["offset"])) for r in wl.reqs]
+        for t in ts:
+            assert s.wait(t)["status"] == 0
+        assert s.stats()["fallbacks"] == wl.reqs.size
+        got = d_out.cpu().numpy()
+    for r in wl.reqs:
+        o, n = int(r["offset"]), int(r["length"])
+        assert first_mismatch(got[o:o + n], oracle_request(wl, r, inp[o:o + n])) is None
+
+
+def test_idle_exit_and_relaunch(ctx):
+    print("[gpu] idle exit and relaunch", flush=True)
+    wl = make_trace(10, seed=9)
+    inp = wl.data()
+    d_in = torch.from_numpy(inp).cuda()
+    d_out = torch.empty_like(d_in)
+    sync()
+    with server(ctx, wl, idle_timeout_ms=30) as s:
+        for i, r in enumerate(wl.reqs):
+            t = submit_retry(s, r, d_in.data_ptr() + int(r["offset"]),
+                             d_out.data_ptr() + int(r["offset"]))
+            assert s.wait(t)["status"] == 0
+            if i % 3 == 2:
+                time.sleep(0.15)  # the kernel exits; the next submit relaunches it
+        assert s.stats()["kernel_launches"] >= 3
+        got = d_out.cpu().numpy()
+    for r in wl.reqs:
+        o, n = int(r["offset"]), int(r["length"])
+        assert first_mismatch(got[o:o + n], oracle_request(wl, r, inp[o:o + n])) is None
+
+
+def test_errors_and_callbacks(ctx):
+    print("[gpu] serving errors and callbacks", flush=True)
+    a = ag()
+    wl = make_trace(20, seed=11)
+    inp = wl.data()
+    d_in = torch.from_numpy(inp).cuda()
+    d_out = torch.empty_like(d_in)
+    sync()
+    iv = np.zeros(16, np.uint8)
+    with server(ctx, wl) as s:
+        p, q = d_in.data_ptr(), d_out.data_ptr()
+        for args, status in (((0, 99, iv, p, q, 4096), a.AES_ERR_RANGE),
+                             ((1, 0, iv, p, q, 4008), a.AES_ERR_LENGTH),
+                             ((2, 0, iv, p, q, 0), a.AES_ERR_ARG),
+                             ((3, 0, iv, p, q, 4096), a.AES_ERR_ARG),
+                             ((2, 0, iv, p, p + 16, 4096), a.AES_ERR_OVERLAP)):
+            with pytest.raises(a.AesError) as e:
+                s.submit(*args)
+            assert e.value.status == status
+        with pytest.raises(a.AesError) as e:
+            s.set_key(10_000, a.expand_key(bytes(16), 128))
+        assert e.value.status == a.AES_ERR_RANGE
+        seen = []
+        for r in wl.reqs:
+            while True:
+                try:
+                    s.submit(int(r["op"]), int(r["key_idx"]), r["iv"], p + int(r["offset"]),
+                             q + int(r["offset"]), int(r["length"]),
+                             callback=lambda rec: seen.append((int(rec["ticket"]),
+                                                               int(rec["status"]))))
+                    break
+                except a.AesError as e2:
+                    assert e2.status == a.AES_ERR_AGAIN
+                    time.sleep(1e-4)
+        deadline = time.time() + 20
+        while len(seen) < wl.reqs.size and time.time() < deadline:
+            time.sleep(1e-3)
+        assert sorted(t for t, _ in seen) == list(range(wl.reqs.size))
+        assert all(st == 0 for _, st in seen)
+        got = d_out.cpu().numpy()
+    for r in wl.reqs:
+        o, n = int(r["offset"]), int(r["length"])
+        assert first_mismatch(got[o:o + n], oracle_request(wl, r, inp[o:o + n])) is None
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_replay_poisson_trace(ctx, engine):
+    print(f"[gpu] replay of a Poisson trace, engine={engine}", flush=True)
+    tr = workloads.config4(20000.0, 400, n_slots=16)
+    wl = workloads.Workload("cfg4", tr.reqs, tr.keys, tr.key_bits, tr.buf_bytes)
+    inp = wl.data()
+    d_in = torch.from_numpy(inp).cuda()
+    d_out = torch.empty_like(d_in)
+    sync()
+    with server(ctx, wl, mode=engine) as s:
+        done = s.replay(tr.reqs, tr.arrivals_s, d_in, d_out)
+        got = d_out.cpu().numpy()
+    assert (done["status"] == 0).all()
+    lat = (done["t_done_ns"] - done["t_submit_ns"]) / 1e3
+    assert (lat > 0).all() and np.median(lat) < 1e5
+    for r in tr.reqs[::5]:
+        o, n = int(r["offset"]), int(r["length"])
+        assert first_mismatch(got[o:o + n], oracle_request(wl, r, inp[o:o + n])) is None
