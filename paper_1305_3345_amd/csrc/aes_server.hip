@@ -137,16 +137,18 @@ __device__ void dispatch_loop(const ServeArgs &a) {
     for (;;) {
         const uint64_t t = next + lane;
         ServeDesc *d = a.ring + (t & a.ring_mask);
-        const uint64_t seq = __hip_atomic_load(&d->seq, __ATOMIC_ACQUIRE, SYS);
+        const uint64_t seq = __hip_atomic_load(&d->seq, __ATOMIC_RELAXED, SYS);
         const uint64_t ready = __ballot(seq == t + 1);
         const uint32_t n_ready = ~ready ? (uint32_t)__builtin_ctzll(~ready) : 64u;
+        if (n_ready)
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
         if (n_ready == 0) {
             if ((++polls & 63u) == 0 && lane == 0)
                 __hip_atomic_store(&a.ctl->heartbeat, (uint64_t)polls, __ATOMIC_RELAXED, SYS);
             const uint32_t stop = __hip_atomic_load(&a.ctl->stop, __ATOMIC_RELAXED, SYS);
             if (stop || now_ticks() - last_work > a.idle_ticks)
                 break;
-            __builtin_amdgcn_s_sleep(4);
+            __builtin_amdgcn_s_sleep(2);
             continue;
         }
         // Lane i < n_ready reads descriptor next + i.
@@ -250,9 +252,12 @@ __device__ void dispatch_loop(const ServeArgs &a) {
     }
 }
 
-// Wave-uniform read of a device-scope counter.
-__device__ __forceinline__ uint64_t load_u64_uniform(uint64_t *p) {
-    const uint64_t v = __hip_atomic_load(p, __ATOMIC_ACQUIRE, AGT);
+// Wave-uniform relaxed read of a device-scope counter.  Polling loops use
+// relaxed loads: an acquire at agent or system scope invalidates caches, and
+// hundreds of idle waves doing that continuously would evict the working
+// waves' data.  The acquire fence comes once, after progress is seen.
+__device__ __forceinline__ uint64_t poll_u64(uint64_t *p) {
+    const uint64_t v = __hip_atomic_load(p, __ATOMIC_RELAXED, AGT);
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
     return ((uint64_t)hi << 32) | lo;
@@ -268,22 +273,31 @@ __device__ __forceinline__ bool claim(const ServeArgs &a, int qi, uint64_t *idx)
     ServeQueue *q = a.q + qi;
     uint64_t got = 0;
     if (lane == 0)
-        got = __hip_atomic_fetch_add(&q->head, 1ull, __ATOMIC_ACQ_REL, AGT);
+        got = __hip_atomic_fetch_add(&q->head, 1ull, __ATOMIC_RELAXED, AGT);
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)got);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(got >> 32));
     const uint64_t pos = ((uint64_t)hi << 32) | lo;
+    uint32_t nap = 1;
     for (;;) {
-        if (pos < load_u64_uniform(&q->tail))
+        if (pos < poll_u64(&q->tail))
             break;
         const uint32_t closed =
-            __builtin_amdgcn_readfirstlane(__hip_atomic_load(a.closed, __ATOMIC_ACQUIRE, AGT));
+            __builtin_amdgcn_readfirstlane(__hip_atomic_load(a.closed, __ATOMIC_RELAXED, AGT));
         if (closed) {
-            if (pos < load_u64_uniform(&q->tail))
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (pos < poll_u64(&q->tail))
                 break;
             return false;
         }
-        __builtin_amdgcn_s_sleep(8);
+        // Back off from about 0.03 to 1 microsecond between polls.
+        if (nap < 16) {
+            __builtin_amdgcn_s_sleep(1);
+            nap++;
+        } else {
+            __builtin_amdgcn_s_sleep(32);
+        }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *idx = pos;
     return true;
 }
