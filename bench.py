@@ -40,6 +40,12 @@ def parse():
                     help="iterations of the host-metadata single-call form (0 = skip)")
     ap.add_argument("--runs", default="cbc_dec_128,ctr_128,cbc_dec_256,ctr_256",
                     help="comma-separated subset of the step's runs (for profiling)")
+    ap.add_argument("--skip-serving", action="store_true",
+                    help="skip the serving (Poisson arrivals, p50/p99) measurement")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="measured requests per arrival rate and engine")
+    ap.add_argument("--skip-variants", action="store_true",
+                    help="skip the table vs bitsliced CTR comparison")
     ap.add_argument("--skip-batched", action="store_true",
                     help="skip the mixed-batch (10,000 uneven requests) measurement")
     ap.add_argument("--calib-copy", action="store_true",
@@ -160,6 +166,111 @@ def bench_batched(dev, iters=3):
     }
 
 
+def bench_variants(ctx, n_pages, d_in, d_out, dev, iters=5):
+    """The CTR kernel variants side by side on the 4 KiB-page workload: round
+    tables in LDS against the bitsliced kernel, AES-128 and AES-256 (plan
+    launches, median of iters, HIP events)."""
+    import torch
+
+    from paper_1305_3345_amd import aesgpu
+    from synth import workloads
+
+    stream = torch.cuda.current_stream()
+    cfg = ctx.get_config()
+    out = {}
+    try:
+        for bits in (128, 256):
+            wl = workloads.config2(workloads.OP_CTR, bits, n_pages=n_pages)
+            d_s = aesgpu.schedules_to_device(aesgpu.expand_keys(wl.keys, wl.key_bits), dev)
+            payload = int(wl.reqs["length"].sum())
+            rec = {}
+            for v, vname in ((aesgpu.AES_CTR_TABLE, "table"), (aesgpu.AES_CTR_BITSLICE, "bitslice")):
+                ctx.set_config(ctr_variant=v)
+                plan = aesgpu.Plan(ctx, wl.reqs, wl.keys.shape[0], wl.buf_bytes)
+                ms = time_gpu(lambda: plan.launch(d_s, d_in, d_out, stream=stream), iters, stream)
+                plan.close()
+                rec[vname] = {"ms": round(ms, 4), "gbs_payload": round(payload / ms / 1e6, 1)}
+            rec["bitslice_over_table"] = round(rec["table"]["ms"] / rec["bitslice"]["ms"], 3)
+            out[f"ctr_{bits}"] = rec
+    finally:
+        ctx.set_config(**cfg)
+    return out
+
+
+def bench_serving(dev, n_measure=2000, n_warm=200):
+    """The serving form: Poisson arrivals, sizes uniform in {4,8,16,32,64} KiB,
+    AES-128-CBC encrypt/decrypt 50/50 over 256 resident key slots, payloads
+    staged in HBM, 256 MiB admission cap.  The per-request-launch engine's
+    saturated throughput (a burst of requests) sets the five offered rates
+    (0.1, 0.25, 0.5, 0.75, 0.9 of it); both engines replay the same trace at
+    each rate; latency = host time from arrival to observed completion."""
+    import numpy as np
+    import torch
+
+    from paper_1305_3345_amd import aesgpu
+    from synth import gen, workloads
+
+    n = n_warm + n_measure
+    tr = workloads.config4(1.0, n)  # arrival times at 1 request/s; scaled per rate
+    nb = (tr.buf_bytes + 7) // 8 * 8
+    d_in = gen.bytes_torch(0, gen.STREAM_DATA, nb, dev)
+    d_out = torch.empty_like(d_in)
+    torch.cuda.current_stream().synchronize()
+    scheds = aesgpu.expand_keys(tr.keys, tr.key_bits)
+    ctx = aesgpu.Context(0)
+    names = {aesgpu.AES_SERVE_PERSISTENT: "persistent", aesgpu.AES_SERVE_PER_LAUNCH: "per_launch"}
+
+    def replay(engine, arrivals):
+        with aesgpu.Server(ctx, mode=engine, key_slots=256) as srv:
+            for i, sc in enumerate(scheds):
+                srv.set_key(i, sc)
+            done = srv.replay(tr.reqs, arrivals, d_in, d_out)
+            st = srv.stats()
+        assert (done["status"] == 0).all(), "serving request failed"
+        return done, st
+
+    def summarize(done):
+        m = done[n_warm:]
+        lat = (m["t_done_ns"].astype(np.int64) - m["t_submit_ns"].astype(np.int64)) / 1e3
+        ops = tr.reqs["op"][n_warm:]
+        span = (m["t_done_ns"].max() - m["t_submit_ns"].min()) / 1e9
+        out = {"p50_us": round(float(np.percentile(lat, 50)), 1),
+               "p99_us": round(float(np.percentile(lat, 99)), 1),
+               "p999_us": round(float(np.percentile(lat, 99.9)), 1),
+               "gbs": round(float(tr.reqs["length"][n_warm:].sum()) / span / 1e9, 3)}
+        for op, nm in ((workloads.OP_CBC_ENC, "enc"), (workloads.OP_CBC_DEC, "dec")):
+            sel = lat[ops == op]
+            out[f"{nm}_p50_us"] = round(float(np.percentile(sel, 50)), 1)
+            out[f"{nm}_p99_us"] = round(float(np.percentile(sel, 99)), 1)
+        gpu = (m["gpu_done_ticks"].astype(np.int64) - m["gpu_dispatch_ticks"].astype(np.int64))
+        if gpu.any():  # persistent engine: device clock, 100 MHz, dispatch -> last unit done
+            for op, nm in ((workloads.OP_CBC_ENC, "enc"), (workloads.OP_CBC_DEC, "dec")):
+                out[f"{nm}_gpu_p50_us"] = round(float(np.percentile(gpu[ops == op], 50)) / 100, 1)
+        return out
+
+    burst = np.zeros(n)
+    sat = {}
+    for engine in (aesgpu.AES_SERVE_PER_LAUNCH, aesgpu.AES_SERVE_PERSISTENT):
+        done, _ = replay(engine, burst)
+        span = (done["t_done_ns"].max() - done["t_submit_ns"].min()) / 1e9
+        sat[names[engine]] = round(n / span, 1)
+    base = sat["per_launch"]
+    rates = []
+    for frac in (0.1, 0.25, 0.5, 0.75, 0.9):
+        rate = frac * base
+        row = {"fraction_of_per_launch_saturation": frac, "rate_req_s": round(rate, 1)}
+        for engine in (aesgpu.AES_SERVE_PER_LAUNCH, aesgpu.AES_SERVE_PERSISTENT):
+            done, st = replay(engine, tr.arrivals_s / rate)
+            row[names[engine]] = summarize(done)
+            if engine == aesgpu.AES_SERVE_PERSISTENT:
+                row[names[engine]]["kernel_launches"] = st["kernel_launches"]
+        rates.append(row)
+    ctx.close()
+    return {"workload": f"{n_measure} measured (+{n_warm} warm-up) requests per rate and engine, "
+                        "Poisson arrivals, 4..64 KiB, AES-128-CBC enc/dec 50/50, 256 key slots",
+            "saturation_req_s": sat, "rates": rates}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -267,6 +378,14 @@ def main():
                     "note": "aes_cbc_decrypt_batch / aes_ctr_batch with host request arrays "
                             "(validation + planning + metadata upload in every call)"}
 
+    variants = None
+    if not args.skip_variants:
+        variants = bench_variants(ctx, n_pages, d_in, d_out, dev)
+
+    serving = None
+    if not args.skip_serving:
+        serving = bench_serving(dev, n_measure=args.serve_requests)
+
     batched = None
     if not args.skip_batched:
         batched = bench_batched(dev)
@@ -297,7 +416,9 @@ def main():
         "cpu_baseline": cpu,
         "per_run": per_run,
         "per_call": per_call,
+        "ctr_variants": variants,
         "batched": batched,
+        "serving": serving,
     }
     for _, _, plan, _, _, _, _ in runs:
         plan.close()

@@ -215,7 +215,8 @@ void aes_plan_destroy(aes_plan_t *plan);
 /* Kernel shapes of a context; read at every launch (tile_bytes when a plan is
  * created).  Defaults: tile 4096, CTR and CBC-decrypt tiles 2 blocks per lane
  * x 1024 threads, chains 64 lanes per wave x 256 threads, fused kernel 2
- * blocks per lane, fuse = 1, grid = 0 (one workgroup per compute unit). */
+ * blocks per lane, fuse = 1, grid = 0 (one workgroup per compute unit),
+ * ctr_variant = AES_CTR_TABLE. */
 typedef struct aes_launch_config {
     uint32_t tile_bytes;  /* bytes per CTR / CBC-decrypt unit: multiple of 1024 */
     uint32_t ctr_nb;      /* CTR tile kernel: 16-byte blocks per lane per step (1, 2, 4) */
@@ -227,8 +228,18 @@ typedef struct aes_launch_config {
     uint32_t mixed_nb;    /* fused mixed-batch kernel: blocks per lane (1, 2) */
     uint32_t fuse;        /* 1: a batch mixing ops runs as one launch; 0: one launch per op */
     uint32_t grid;        /* workgroups of tile and fused kernels; 0 = one per compute unit */
-    uint32_t reserved[6];
+    uint32_t ctr_variant; /* CTR units of batches and plans: AES_CTR_TABLE or AES_CTR_BITSLICE */
+    uint32_t reserved[5];
 } aes_launch_config_t;
+
+/* CTR kernel variants.  AES_CTR_TABLE: round tables in LDS, one block per
+ * lane per step (paper section 3.2).  AES_CTR_BITSLICE: no tables; each lane
+ * holds 32 counter blocks as 128 bit planes and computes SubBytes as a Boolean
+ * circuit over the tower field GF((2^4)^2); the planner orders CTR tiles by
+ * key so that the 8 tiles a wave works share one key schedule.  Per-request
+ * launches and the serving engines always use the table kernels. */
+#define AES_CTR_TABLE 0u
+#define AES_CTR_BITSLICE 1u
 
 int aes_ctx_get_config(const aes_ctx_t *ctx, aes_launch_config_t *cfg);
 /* Errors: AES_ERR_ARG for an unsupported shape (nothing changes). */
@@ -236,8 +247,8 @@ int aes_ctx_set_config(aes_ctx_t *ctx, const aes_launch_config_t *cfg);
 
 /* Autotuner: times plan launches of reqs on the caller's buffers (d_in must
  * differ from d_out; d_out is overwritten with the batch's result) for tile
- * sizes, tile-kernel shapes, chain lanes and the fusion switch by coordinate
- * descent (median of iters launches each), leaves the fastest configuration
+ * sizes, tile-kernel shapes, chain lanes, the fusion switch and (for batches
+ * with CTR requests) the CTR variant by coordinate descent (median of iters launches each), leaves the fastest configuration
  * set in ctx and copies it to *best (may be NULL).  Plans created afterwards
  * use its tile size.  Errors: as aes_batch; AES_ERR_OVERLAP if d_in == d_out. */
 int aes_tune(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_scheds,

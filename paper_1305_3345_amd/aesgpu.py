@@ -38,6 +38,8 @@ AES_OP_CBC_ENC = 0
 AES_OP_CBC_DEC = 1
 AES_OP_CTR = 2
 AES_DEVICE_NONE = -1
+AES_CTR_TABLE = 0
+AES_CTR_BITSLICE = 1
 
 SCHED_DTYPE = np.dtype([("key_bits", "<u4"), ("nr", "<u4"), ("reserved0", "<u4", (2,)),
                         ("ek", "<u4", (60,)), ("dk", "<u4", (60,)), ("reserved1", "<u4", (4,))])
@@ -51,7 +53,7 @@ PLAN_INFO_DTYPE = np.dtype([("n_units_cbc_dec", "<u8"), ("n_units_ctr", "<u8"),
                             ("reserved", "<u4")])
 CONFIG_DTYPE = np.dtype([(k, "<u4") for k in (
     "tile_bytes", "ctr_nb", "ctr_wg", "dec_nb", "dec_wg", "chain_lanes", "chain_wg", "mixed_nb",
-    "fuse", "grid")] + [("reserved", "<u4", (6,))])
+    "fuse", "grid", "ctr_variant")] + [("reserved", "<u4", (5,))])
 assert CONFIG_DTYPE.itemsize == 64
 assert SCHED_DTYPE.itemsize == 512 and REQ_DTYPE.itemsize == 40 and UNIT_DTYPE.itemsize == 32
 

@@ -202,6 +202,11 @@ int plan_units(const aes_req_t *reqs, uint64_t n, uint32_t tile_bytes, Planned &
                 }
             }
         }
+        // CTR tiles grouped by key (request order kept within a key): the
+        // bitsliced kernel shares one key schedule across a wave's 8 tiles.
+        std::stable_sort(p.ctr.begin(), p.ctr.end(), [](const Unit &a, const Unit &b) {
+            return (a.meta & META_KEY_MASK) < (b.meta & META_KEY_MASK);
+        });
         // Longest chain first: a chain's lane finishes last, so the longest
         // ones start first and neighbouring lanes get similar lengths.
         std::stable_sort(p.chains.begin(), p.chains.end(),
@@ -238,6 +243,7 @@ struct aes_ctx {
     int mixed_nb = 2;
     bool fuse = true;        // one launch for batches that mix ops
     int grid = 0;            // tile / fused kernel workgroups, 0 = one per compute unit
+    uint32_t ctr_variant = AES_CTR_TABLE;
     hipStream_t capture = nullptr;  // private stream for graph capture and tuning
 };
 
@@ -315,7 +321,14 @@ int launch_planned(aes_ctx *ctx, const PlanView &v, const aes_schedule_t *d_sche
         if ((e = launch_snapshot_preds(u_dec, (uint32_t)v.n_dec, d_in, d_preds, stream)))
             return hip_fail((hipError_t)e);
     }
-    const int kinds = (v.n_dec > 0) + (v.n_ctr > 0) + (v.n_chain > 0);
+    // The bitsliced CTR kernel has a launch of its own; the fused kernel then
+    // takes only the CBC units.
+    const bool bitslice = ctx->ctr_variant == AES_CTR_BITSLICE && v.n_ctr;
+    if (bitslice && (e = launch_ctr_bitslice(u_ctr, (uint32_t)v.n_ctr, d_scheds, n_scheds, d_in,
+                                             d_out, ctx->n_cu, stream)))
+        return hip_fail((hipError_t)e);
+    const size_t n_ctr_tab = bitslice ? 0 : v.n_ctr;
+    const int kinds = (v.n_dec > 0) + (n_ctr_tab > 0) + (v.n_chain > 0);
     if (ctx->fuse && kinds > 1) {
         const int grid = ctx->grid > 0 ? ctx->grid : ctx->n_cu;
         MixedArgs a;
@@ -328,10 +341,13 @@ int launch_planned(aes_ctx *ctx, const PlanView &v, const aes_schedule_t *d_sche
         a.in = d_in;
         a.out = d_out;
         a.n_dec = (uint32_t)v.n_dec;
-        a.n_ctr = (uint32_t)v.n_ctr;
+        a.n_ctr = (uint32_t)n_ctr_tab;
         a.n_chain = (uint32_t)v.n_chain;
         a.n_sched = n_scheds;
-        a.n_dec_wg = dec_workgroups(v, grid);
+        PlanView fused = v;
+        fused.n_ctr = n_ctr_tab;
+        fused.ctr_bytes = bitslice ? 0 : v.ctr_bytes;
+        a.n_dec_wg = dec_workgroups(fused, grid);
         a.chain_lanes = (uint32_t)ctx->chain.lanes;
         if ((e = launch_mixed(a, ctx->mixed_nb, grid, stream)))
             return hip_fail((hipError_t)e);
@@ -340,7 +356,7 @@ int launch_planned(aes_ctx *ctx, const PlanView &v, const aes_schedule_t *d_sche
     if ((e = launch_cbcdec_tiles(u_dec, (uint32_t)v.n_dec, d_scheds, n_scheds, ctx->d_timg,
                                  d_preds, d_in, d_out, ctx->tile_dec, ctx->n_cu, stream)))
         return hip_fail((hipError_t)e);
-    if ((e = launch_ctr_tiles(u_ctr, (uint32_t)v.n_ctr, d_scheds, n_scheds, ctx->d_timg, d_in,
+    if ((e = launch_ctr_tiles(u_ctr, (uint32_t)n_ctr_tab, d_scheds, n_scheds, ctx->d_timg, d_in,
                               d_out, ctx->tile_ctr, ctx->n_cu, stream)))
         return hip_fail((hipError_t)e);
     if ((e = launch_cbcenc_chains(u_chain, (uint32_t)v.n_chain, d_scheds, n_scheds, ctx->d_timg,
@@ -698,6 +714,7 @@ int aes_ctx_get_config(const aes_ctx_t *ctx, aes_launch_config_t *cfg) {
     cfg->mixed_nb = (uint32_t)ctx->mixed_nb;
     cfg->fuse = ctx->fuse ? 1u : 0u;
     cfg->grid = (uint32_t)ctx->grid;
+    cfg->ctr_variant = ctx->ctr_variant;
     return AES_OK;
 }
 
@@ -716,6 +733,8 @@ int aes_ctx_set_config(aes_ctx_t *ctx, const aes_launch_config_t *cfg) {
         return AES_ERR_ARG;
     if (cfg->fuse > 1 || cfg->grid > 65535)
         return AES_ERR_ARG;
+    if (cfg->ctr_variant != AES_CTR_TABLE && cfg->ctr_variant != AES_CTR_BITSLICE)
+        return AES_ERR_ARG;
     ctx->tile_bytes = cfg->tile_bytes;
     ctx->tile_ctr.nb = (int)cfg->ctr_nb;
     ctx->tile_ctr.wg_threads = (int)cfg->ctr_wg;
@@ -728,6 +747,7 @@ int aes_ctx_set_config(aes_ctx_t *ctx, const aes_launch_config_t *cfg) {
     ctx->mixed_nb = (int)cfg->mixed_nb;
     ctx->fuse = cfg->fuse != 0;
     ctx->grid = (int)cfg->grid;
+    ctx->ctr_variant = cfg->ctr_variant;
     return AES_OK;
 }
 
@@ -971,7 +991,8 @@ int aes_tune(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_
         return AES_OK;
     };
     // Coordinate descent: tile size, then each kernel's shape, then the chain
-    // lanes and the fusion switch, each from the best point so far.
+    // lanes, the fusion switch and the CTR variant, each from the best point
+    // so far.
     aes_launch_config_t c = best;
     st = trial(c);
     const uint32_t tiles[] = {4096, 8192, 16384};
@@ -1006,6 +1027,15 @@ int aes_tune(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_
     for (uint32_t f = 0; f <= 1 && !st; f++) {
         c = best;
         c.fuse = f;
+        st = trial(c);
+    }
+    // The CTR kernel variant, when the batch has CTR requests.
+    bool has_ctr = false;
+    for (uint64_t i = 0; i < n_reqs && !has_ctr; i++)
+        has_ctr = reqs[i].op == AES_OP_CTR && reqs[i].length;
+    for (uint32_t v = AES_CTR_TABLE; v <= AES_CTR_BITSLICE && has_ctr && !st; v++) {
+        c = best;
+        c.ctr_variant = v;
         st = trial(c);
     }
     aes_plan_destroy(plan);

@@ -208,6 +208,14 @@ def _check_plan(ag, plan, reqs, tile):
     assert (op_of[k:k + info["n_units_ctr"]] == ag.AES_OP_CTR).all()
     ch = units[k + info["n_units_ctr"]:]
     assert (np.diff(ch["nbytes"].astype(np.int64)) <= 0).all()
+    # CTR tiles grouped by key, request order kept within a key
+    ctr = units[k:k + info["n_units_ctr"]]
+    key_of = (ctr["meta"] & 0xFFFFFF).astype(np.int64)
+    assert (np.diff(key_of) >= 0).all()
+    for key in np.unique(key_of):
+        mine = ctr[key_of == key]
+        assert (np.diff(mine["offset"].astype(np.int64)) > 0).all() or \
+            not np.array_equal(np.sort(reqs["offset"]), reqs["offset"])
 
 
 def test_plan_covers_config3_batch(ag, hctx):
@@ -244,3 +252,20 @@ def test_plan_unsorted_requests(ag, hctx):
     plan = ag.Plan(hctx, wl.reqs[perm], wl.keys.shape[0], wl.buf_bytes)
     _check_plan(ag, plan, wl.reqs[perm], 4096)
     plan.close()
+
+
+def test_launch_config_validation(ag, hctx):
+    """Launch configurations are checked and stored without a device."""
+    cfg = hctx.get_config()
+    assert cfg["tile_bytes"] == 4096 and cfg["ctr_variant"] == ag.AES_CTR_TABLE
+    hctx.set_config(ctr_variant=ag.AES_CTR_BITSLICE, tile_bytes=8192)
+    got = hctx.get_config()
+    assert got["ctr_variant"] == ag.AES_CTR_BITSLICE and got["tile_bytes"] == 8192
+    for bad in ({"ctr_variant": 2}, {"tile_bytes": 1000}, {"ctr_nb": 3}, {"chain_lanes": 0},
+                {"mixed_nb": 4}, {"fuse": 2}):
+        with pytest.raises(ag.AesError) as e:
+            hctx.set_config(**bad)
+        assert e.value.status == ag.AES_ERR_ARG
+        assert hctx.get_config() == got  # nothing changes on error
+    hctx.set_config(**cfg)
+    assert hctx.get_config() == cfg
