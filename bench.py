@@ -46,6 +46,8 @@ def parse():
                     help="measured requests per arrival rate and engine")
     ap.add_argument("--skip-variants", action="store_true",
                     help="skip the table vs bitsliced CTR comparison")
+    ap.add_argument("--skip-long", action="store_true",
+                    help="skip the 8 GiB CTR stream and the 4,096 CBC-encrypt chains")
     ap.add_argument("--skip-batched", action="store_true",
                     help="skip the mixed-batch (10,000 uneven requests) measurement")
     ap.add_argument("--calib-copy", action="store_true",
@@ -195,6 +197,48 @@ def bench_variants(ctx, n_pages, d_in, d_out, dev, iters=5):
     finally:
         ctx.set_config(**cfg)
     return out
+
+
+def bench_long(dev, iters=3):
+    """The long-stream workloads: AES-256-CTR over 8 GiB in HBM as 512 chunks
+    of 16 MiB (one continuous counter stream), as one plan launch and as 512
+    per-request launches; and AES-256-CBC encryption of 4,096 chains of 1 MiB
+    (the serial-chain limit) as one launch."""
+    import torch
+
+    from paper_1305_3345_amd import aesgpu
+    from synth import gen, workloads
+
+    stream = torch.cuda.current_stream()
+    ctx = aesgpu.Context(0)
+    wl = workloads.config5_ctr()
+    nbytes = wl.buf_bytes
+    d_in = gen.bytes_torch(0, gen.STREAM_DATA, nbytes, dev)
+    d_out = torch.empty_like(d_in)
+    d_s = aesgpu.schedules_to_device(aesgpu.expand_keys(wl.keys, wl.key_bits), dev)
+    plan = aesgpu.Plan(ctx, wl.reqs, 1, nbytes)
+    ctr_ms = time_gpu(lambda: plan.launch(d_s, d_in, d_out, stream=stream), iters, stream)
+    plan.close()
+    each_ms = time_gpu(lambda: aesgpu.request_launches(ctx, d_s, d_in, d_out, wl.reqs,
+                                                       stream=stream), iters, stream)
+    wc = workloads.config5_cbc()
+    d_sc = aesgpu.schedules_to_device(aesgpu.expand_keys(wc.keys, wc.key_bits), dev)
+    pc = aesgpu.Plan(ctx, wc.reqs, 1, wc.buf_bytes)
+    cbc_ms = time_gpu(lambda: pc.launch(d_sc, d_in, d_out, stream=stream), 2, stream)
+    pc.close()
+    ctx.close()
+    del d_in, d_out
+    torch.cuda.empty_cache()
+    gbs = lambda b, ms: round(b / ms / 1e6, 1)
+    return {
+        "ctr256_8gib": {"chunks": int(wl.reqs.size), "bytes": nbytes,
+                        "one_launch_ms": round(ctr_ms, 3), "one_launch_gbs": gbs(nbytes, ctr_ms),
+                        "per_chunk_launches_ms": round(each_ms, 3),
+                        "per_chunk_launches_gbs": gbs(nbytes, each_ms)},
+        "cbcenc256_4096x1mib": {"chains": int(wc.reqs.size), "bytes": wc.buf_bytes,
+                                "one_launch_ms": round(cbc_ms, 3),
+                                "gbs": gbs(wc.buf_bytes, cbc_ms)},
+    }
 
 
 def bench_serving(dev, n_measure=2000, n_warm=200):
@@ -390,6 +434,10 @@ def main():
     if not args.skip_batched:
         batched = bench_batched(dev)
 
+    long_stream = None
+    if not args.skip_long:
+        long_stream = bench_long(dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(min(args.cpu_sample_pages, n_pages))
@@ -418,6 +466,7 @@ def main():
         "per_call": per_call,
         "ctr_variants": variants,
         "batched": batched,
+        "long_stream": long_stream,
         "serving": serving,
     }
     for _, _, plan, _, _, _, _ in runs:
