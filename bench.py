@@ -342,7 +342,13 @@ def main():
 
     runs = []  # (name, kernel, plan, d_scheds, payload, units)
     for bits in (128, 256):
-        for op, kname in ((workloads.OP_CBC_DEC, "cbcdec_tiles"), (workloads.OP_CTR, "ctr_tiles")):
+        cfg = ctx.get_config()
+        kernels = {workloads.OP_CBC_DEC: f"k_tiles<true, {cfg['dec_nb']}, {cfg['dec_wg']}>",
+                   workloads.OP_CTR: (f"k_tiles<false, {cfg['ctr_nb']}, {cfg['ctr_wg']}>"
+                                      if cfg["ctr_variant"] == aesgpu.AES_CTR_TABLE
+                                      else "k_ctr_bitslice")}
+        for op, kname in ((workloads.OP_CBC_DEC, kernels[workloads.OP_CBC_DEC]),
+                          (workloads.OP_CTR, kernels[workloads.OP_CTR])):
             name = f"{workloads.OP_NAMES[op]}_{bits}"
             if name not in args.runs.split(","):
                 continue
@@ -400,7 +406,7 @@ def main():
     achieved = algo_per_launch / avg_ms / 1e6
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": f"k_{dom}", "avg_launch_ms": round(avg_ms, 4),
+                "kernel": f"aesgpu::{dom}", "avg_launch_ms": round(avg_ms, 4),
                 "algo_bytes_per_launch": int(algo_per_launch)}
 
     # Host-metadata single-call form: validation, planning and the unit-table

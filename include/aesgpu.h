@@ -213,9 +213,10 @@ void aes_plan_destroy(aes_plan_t *plan);
 /* ------------------------------------------------------- launch configuration */
 
 /* Kernel shapes of a context; read at every launch (tile_bytes when a plan is
- * created).  Defaults: tile 4096, CTR and CBC-decrypt tiles 2 blocks per lane
- * x 1024 threads, chains 64 lanes per wave x 256 threads, fused kernel 2
- * blocks per lane, fuse = 1, grid = 0 (one workgroup per compute unit),
+ * created).  Defaults: tile 4096, CTR tiles 2 blocks per lane x 1024 threads,
+ * CBC-decrypt tiles 1 block per lane x 1024 threads, chains four lanes each
+ * (chain_quad = 1; chain_lanes = 64 when it is 0) x 256 threads, fused kernel
+ * 2 blocks per lane, fuse = 1, grid = 0 (one workgroup per compute unit),
  * ctr_variant = AES_CTR_TABLE. */
 typedef struct aes_launch_config {
     uint32_t tile_bytes;  /* bytes per CTR / CBC-decrypt unit: multiple of 1024 */
@@ -229,7 +230,10 @@ typedef struct aes_launch_config {
     uint32_t fuse;        /* 1: a batch mixing ops runs as one launch; 0: one launch per op */
     uint32_t grid;        /* workgroups of tile and fused kernels; 0 = one per compute unit */
     uint32_t ctr_variant; /* CTR units of batches and plans: AES_CTR_TABLE or AES_CTR_BITSLICE */
-    uint32_t reserved[5];
+    uint32_t chain_quad;  /* CBC-encrypt chains: 0 = chain_lanes chains per wave, one lane each;
+                             1 = 16 chains per wave, four lanes each (one state column per
+                             lane: a quarter of the lookups per lane per round) */
+    uint32_t reserved[4];
 } aes_launch_config_t;
 
 /* CTR kernel variants.  AES_CTR_TABLE: round tables in LDS, one block per
@@ -247,8 +251,9 @@ int aes_ctx_set_config(aes_ctx_t *ctx, const aes_launch_config_t *cfg);
 
 /* Autotuner: times plan launches of reqs on the caller's buffers (d_in must
  * differ from d_out; d_out is overwritten with the batch's result) for tile
- * sizes, tile-kernel shapes, chain lanes, the fusion switch and (for batches
- * with CTR requests) the CTR variant by coordinate descent (median of iters launches each), leaves the fastest configuration
+ * sizes, tile-kernel shapes, chain lanes or four-lane chains, the fusion
+ * switch and (for batches with CTR requests) the CTR variant by coordinate
+ * descent (median of iters launches each), leaves the fastest configuration
  * set in ctx and copies it to *best (may be NULL).  Plans created afterwards
  * use its tile size.  Errors: as aes_batch; AES_ERR_OVERLAP if d_in == d_out. */
 int aes_tune(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_scheds,

@@ -53,7 +53,7 @@ PLAN_INFO_DTYPE = np.dtype([("n_units_cbc_dec", "<u8"), ("n_units_ctr", "<u8"),
                             ("reserved", "<u4")])
 CONFIG_DTYPE = np.dtype([(k, "<u4") for k in (
     "tile_bytes", "ctr_nb", "ctr_wg", "dec_nb", "dec_wg", "chain_lanes", "chain_wg", "mixed_nb",
-    "fuse", "grid", "ctr_variant")] + [("reserved", "<u4", (5,))])
+    "fuse", "grid", "ctr_variant", "chain_quad")] + [("reserved", "<u4", (4,))])
 assert CONFIG_DTYPE.itemsize == 64
 assert SCHED_DTYPE.itemsize == 512 and REQ_DTYPE.itemsize == 40 and UNIT_DTYPE.itemsize == 32
 

@@ -238,8 +238,9 @@ struct aes_ctx {
     Slot slots[N_SLOTS];
     int next_slot = 0;
     uint32_t tile_bytes = DEFAULT_TILE;
-    TileLaunch tile_ctr, tile_dec;
-    ChainLaunch chain;
+    TileLaunch tile_ctr;
+    TileLaunch tile_dec{1, 1024, 0};  // one block per lane: fewer registers for the 14-round keys
+    ChainLaunch chain{256, 64, true, 0};  // four lanes per chain
     int mixed_nb = 2;
     bool fuse = true;        // one launch for batches that mix ops
     int grid = 0;            // tile / fused kernel workgroups, 0 = one per compute unit
@@ -349,6 +350,7 @@ int launch_planned(aes_ctx *ctx, const PlanView &v, const aes_schedule_t *d_sche
         fused.ctr_bytes = bitslice ? 0 : v.ctr_bytes;
         a.n_dec_wg = dec_workgroups(fused, grid);
         a.chain_lanes = (uint32_t)ctx->chain.lanes;
+        a.chain_quad = ctx->chain.quad ? 1u : 0u;
         if ((e = launch_mixed(a, ctx->mixed_nb, grid, stream)))
             return hip_fail((hipError_t)e);
         return AES_OK;
@@ -711,6 +713,7 @@ int aes_ctx_get_config(const aes_ctx_t *ctx, aes_launch_config_t *cfg) {
     cfg->dec_wg = (uint32_t)ctx->tile_dec.wg_threads;
     cfg->chain_lanes = (uint32_t)ctx->chain.lanes;
     cfg->chain_wg = (uint32_t)ctx->chain.wg_threads;
+    cfg->chain_quad = ctx->chain.quad ? 1u : 0u;
     cfg->mixed_nb = (uint32_t)ctx->mixed_nb;
     cfg->fuse = ctx->fuse ? 1u : 0u;
     cfg->grid = (uint32_t)ctx->grid;
@@ -735,6 +738,8 @@ int aes_ctx_set_config(aes_ctx_t *ctx, const aes_launch_config_t *cfg) {
         return AES_ERR_ARG;
     if (cfg->ctr_variant != AES_CTR_TABLE && cfg->ctr_variant != AES_CTR_BITSLICE)
         return AES_ERR_ARG;
+    if (cfg->chain_quad > 1)
+        return AES_ERR_ARG;
     ctx->tile_bytes = cfg->tile_bytes;
     ctx->tile_ctr.nb = (int)cfg->ctr_nb;
     ctx->tile_ctr.wg_threads = (int)cfg->ctr_wg;
@@ -744,6 +749,7 @@ int aes_ctx_set_config(aes_ctx_t *ctx, const aes_launch_config_t *cfg) {
     ctx->tile_dec.grid = (int)cfg->grid;
     ctx->chain.lanes = (int)cfg->chain_lanes;
     ctx->chain.wg_threads = (int)cfg->chain_wg;
+    ctx->chain.quad = cfg->chain_quad != 0;
     ctx->mixed_nb = (int)cfg->mixed_nb;
     ctx->fuse = cfg->fuse != 0;
     ctx->grid = (int)cfg->grid;
@@ -1022,6 +1028,12 @@ int aes_tune(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_
             break;
         c = best;
         c.chain_lanes = l;
+        c.chain_quad = 0;
+        st = trial(c);
+    }
+    if (!st) {  // four lanes per chain
+        c = best;
+        c.chain_quad = 1;
         st = trial(c);
     }
     for (uint32_t f = 0; f <= 1 && !st; f++) {

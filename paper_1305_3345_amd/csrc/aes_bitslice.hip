@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256, 2) void k_ctr_bitslice(const Unit *__restrict_
     const uint32_t g = lane >> 3, sub = lane & 7u;
     const uint32_t wpb = blockDim.x >> 6;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
-    const uint32_t nw = gridDim.x * wpb;
+    const uint32_t nw = __builtin_amdgcn_readfirstlane(gridDim.x * wpb);
     const uint32_t n_groups = (n_units + 7u) / 8u;
     for (uint32_t grp = wave; grp < n_groups; grp += nw) {
         const uint32_t u = grp * 8u + g;

@@ -22,18 +22,20 @@ __global__ __launch_bounds__(WG) void k_tiles(const Unit *__restrict__ units, ui
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t L0 = (lane & 31u) << 2;
-    const uint32_t L1 = L0 | 0x10000u;
     const uint32_t L2 = L0 | SI_BASE;
-    const uint32_t wpb = blockDim.x >> 6;
+    // Waves per workgroup from the template (the kernel is launched with WG
+    // threads), and the wave index and stride made explicitly uniform: the
+    // unit loop, its record and key-schedule loads stay scalar.
+    constexpr uint32_t wpb = WG / 64;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
-    const uint32_t nw = gridDim.x * wpb;
+    const uint32_t nw = __builtin_amdgcn_readfirstlane(gridDim.x * wpb);
     for (uint32_t u = wave; u < n_units; u += nw) {
         const Unit un = units[u];
         if (DEC)
-            run_dec_unit<NB>(lds, L0, L1, L2, lane, un, preds ? preds + u : nullptr, sched,
+            run_dec_unit<NB>(lds, L0, L2, lane, un, preds ? preds + u : nullptr, sched,
                              n_sched, in, out);
         else
-            run_ctr_unit<NB>(lds, L0, L1, lane, un, sched, n_sched, in, out);
+            run_ctr_unit<NB>(lds, L0, lane, un, sched, n_sched, in, out);
     }
 }
 
@@ -42,6 +44,8 @@ __device__ __forceinline__ uint32_t spread_wave(uint32_t wg, uint32_t n_wg) {
     return __builtin_amdgcn_readfirstlane((threadIdx.x >> 6) * n_wg + wg);
 }
 
+// CBC-encrypt chains: cl chains per wave on one lane each, or (cl = 0) 16
+// chains per wave on four lanes each.
 __global__ __launch_bounds__(1024) void k_chains(const Unit *__restrict__ chains,
                                                  uint32_t n_chain, uint32_t cl,
                                                  const aes_schedule_t *__restrict__ sched,
@@ -53,10 +57,12 @@ __global__ __launch_bounds__(1024) void k_chains(const Unit *__restrict__ chains
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t L0 = (lane & 31u) << 2;
-    const uint32_t L1 = L0 | 0x10000u;
-    const uint32_t n_waves = gridDim.x * (blockDim.x >> 6);
-    chain_loop(lds, L0, L1, lane, spread_wave(blockIdx.x, gridDim.x), n_waves, cl, chains,
-               n_chain, sched, n_sched, in, out);
+    const uint32_t n_waves = __builtin_amdgcn_readfirstlane(gridDim.x * (blockDim.x >> 6));
+    const uint32_t e = spread_wave(blockIdx.x, gridDim.x);
+    if (cl)
+        chain_loop(lds, L0, lane, e, n_waves, cl, chains, n_chain, sched, n_sched, in, out);
+    else
+        chain_loop_quad(lds, L0, lane, e, n_waves, chains, n_chain, sched, n_sched, in, out);
 }
 
 // ----------------------------------------------------- one fused launch
@@ -70,16 +76,15 @@ __global__ __launch_bounds__(1024) void k_mixed(MixedArgs a) {
     __shared__ uint32_t lds[LDS_DEC_WORDS];
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t L0 = (lane & 31u) << 2;
-    const uint32_t L1 = L0 | 0x10000u;
     const uint32_t L2 = L0 | SI_BASE;
     const uint32_t wpb = blockDim.x >> 6;
     if (blockIdx.x < a.n_dec_wg) {
         fill_tables<true>(lds, a.timg);
         __syncthreads();
-        const uint32_t nw = a.n_dec_wg * wpb;
+        const uint32_t nw = __builtin_amdgcn_readfirstlane(a.n_dec_wg * wpb);
         for (uint32_t u = spread_wave(blockIdx.x, a.n_dec_wg); u < a.n_dec; u += nw) {
             const Unit un = a.dec[u];
-            run_dec_unit<NB>(lds, L0, L1, L2, lane, un,
+            run_dec_unit<NB>(lds, L0, L2, lane, un,
                              a.preds ? reinterpret_cast<const uint4 *>(a.preds) + u : nullptr,
                              a.sched, a.n_sched, a.in, a.out);
         }
@@ -89,18 +94,23 @@ __global__ __launch_bounds__(1024) void k_mixed(MixedArgs a) {
     __syncthreads();
     const uint32_t n_enc_wg = gridDim.x - a.n_dec_wg;
     const uint32_t e = spread_wave(blockIdx.x - a.n_dec_wg, n_enc_wg);
-    const uint32_t nw = n_enc_wg * wpb;
+    const uint32_t nw = __builtin_amdgcn_readfirstlane(n_enc_wg * wpb);
     if (a.n_chain) {
-        const uint32_t chain_waves = (uint32_t)(((uint64_t)a.n_chain + a.chain_lanes - 1) /
-                                                a.chain_lanes);
+        const uint32_t per_wave = a.chain_quad ? 16u : a.chain_lanes;
+        const uint32_t chain_waves = (uint32_t)(((uint64_t)a.n_chain + per_wave - 1) / per_wave);
         const uint32_t cw = chain_waves < nw ? chain_waves : nw;
-        if (e < cw)
-            chain_loop(lds, L0, L1, lane, e, cw, a.chain_lanes, a.chains, a.n_chain, a.sched,
-                       a.n_sched, a.in, a.out);
+        if (e < cw) {
+            if (a.chain_quad)
+                chain_loop_quad(lds, L0, lane, e, cw, a.chains, a.n_chain, a.sched, a.n_sched,
+                                a.in, a.out);
+            else
+                chain_loop(lds, L0, lane, e, cw, a.chain_lanes, a.chains, a.n_chain, a.sched,
+                           a.n_sched, a.in, a.out);
+        }
     }
     for (uint32_t u = e; u < a.n_ctr; u += nw) {
         const Unit un = a.ctr[u];
-        run_ctr_unit<NB>(lds, L0, L1, lane, un, a.sched, a.n_sched, a.in, a.out);
+        run_ctr_unit<NB>(lds, L0, lane, un, a.sched, a.n_sched, a.in, a.out);
     }
 }
 
@@ -140,7 +150,7 @@ __device__ __forceinline__ Unit request_unit(const aes_req_t &r, uint32_t t, uin
 }
 
 template <bool DEC, int NB>
-__global__ __launch_bounds__(256) void k_request(aes_req_t r, uint32_t tile,
+__global__ __launch_bounds__(1024) void k_request(aes_req_t r, uint32_t tile,
                                                  const aes_schedule_t *__restrict__ sched,
                                                  uint32_t n_sched,
                                                  const uint32_t *__restrict__ timg,
@@ -150,27 +160,25 @@ __global__ __launch_bounds__(256) void k_request(aes_req_t r, uint32_t tile,
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t L0 = (lane & 31u) << 2;
-    const uint32_t L1 = L0 | 0x10000u;
     const uint32_t L2 = L0 | SI_BASE;
     if (!DEC && r.op == AES_OP_CBC_ENC) {
-        // One serial chain: the first wave runs it on all lanes in lockstep
-        // (identical results and stores), keeping its control flow uniform.
+        // One serial chain, on four lanes of the first wave.
         if (blockIdx.x == 0 && threadIdx.x < 64u) {
             const Unit un = request_unit(r, 0, (uint32_t)r.length);
-            run_chain(lds, L0, L1, un, sched, n_sched, in, out);
+            run_chain_quad(lds, L0, lane, un, sched, n_sched, in, out);
         }
         return;
     }
     const uint32_t wpb = blockDim.x >> 6;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
-    const uint32_t nw = gridDim.x * wpb;
+    const uint32_t nw = __builtin_amdgcn_readfirstlane(gridDim.x * wpb);
     const uint32_t n_units = (uint32_t)((r.length + tile - 1) / tile);
     for (uint32_t t = wave; t < n_units; t += nw) {
         const Unit un = request_unit(r, t, tile);
         if (DEC)
-            run_dec_unit<NB>(lds, L0, L1, L2, lane, un, nullptr, sched, n_sched, in, out);
+            run_dec_unit<NB>(lds, L0, L2, lane, un, nullptr, sched, n_sched, in, out);
         else
-            run_ctr_unit<NB>(lds, L0, L1, lane, un, sched, n_sched, in, out);
+            run_ctr_unit<NB>(lds, L0, lane, un, sched, n_sched, in, out);
     }
 }
 
@@ -258,7 +266,7 @@ int launch_cbcenc_chains(const Unit *d_units, uint32_t n_units, const aes_schedu
         return hipSuccess;
     const uint32_t cl = cfg.lanes < 1 ? 64u : (cfg.lanes > 64 ? 64u : (uint32_t)cfg.lanes);
     const int wpb = cfg.wg_threads / 64;
-    const uint32_t waves = chain_waves_needed(n_units, cl);
+    const uint32_t waves = chain_waves_needed(n_units, cfg.quad ? 16u : cl);
     int grid = cfg.grid > 0 ? cfg.grid : (int)((waves + wpb - 1) / wpb);
     if (grid > n_cu && cfg.grid <= 0)
         grid = n_cu;
@@ -270,8 +278,8 @@ int launch_cbcenc_chains(const Unit *d_units, uint32_t n_units, const aes_schedu
         grid = (int)((waves + per_cu - 1) / per_cu);
     }
     hipLaunchKernelGGL(k_chains, dim3(grid < 1 ? 1 : grid), dim3(threads), 0,
-                       (hipStream_t)stream, d_units, n_units, cl, d_sched, n_sched, d_timg, d_in,
-                       d_out);
+                       (hipStream_t)stream, d_units, n_units, cfg.quad ? 0u : cl, d_sched, n_sched,
+                       d_timg, d_in, d_out);
     return hipGetLastError();
 }
 
@@ -281,7 +289,7 @@ int launch_mixed(const MixedArgs &a, int nb, int grid, void *stream) {
     void (*k)(MixedArgs) = nb == 1 ? &k_mixed<1> : (nb == 2 ? &k_mixed<2> : nullptr);
     if (!k || grid < 1 || (a.n_dec && a.n_dec_wg < 1) ||
         ((a.n_ctr || a.n_chain) && (uint32_t)grid <= a.n_dec_wg) || a.chain_lanes < 1 ||
-        a.chain_lanes > 64)
+        a.chain_lanes > 64 || a.chain_quad > 1)
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k, dim3(grid), dim3(1024), 0, (hipStream_t)stream, a);
     return hipGetLastError();
@@ -292,17 +300,27 @@ int launch_request(const aes_req_t &r, uint32_t tile, const aes_schedule_t *d_sc
                    uint8_t *d_out, int n_cu, void *stream) {
     if (!r.length)
         return hipSuccess;
-    // One wave per workgroup and one tile per workgroup (up to one per
-    // compute unit): a request's tiles spread over as many compute units as
-    // it has tiles.
+    // A request's tiles spread over as many compute units as it has tiles
+    // (one single-wave workgroup per tile for small requests); larger
+    // requests get up to 16 waves per workgroup and up to two workgroups per
+    // compute unit in the grid.
     const uint32_t n_units = (uint32_t)((r.length + tile - 1) / tile);
-    int grid = r.op == AES_OP_CBC_ENC ? 1 : (int)(n_units < (uint32_t)n_cu ? n_units : n_cu);
+    const uint32_t cus = (uint32_t)n_cu;
+    uint32_t waves = (n_units + cus - 1) / cus;
+    waves = waves < 1u ? 1u : (waves > 16u ? 16u : waves);
+    uint32_t grid = (n_units + waves - 1) / waves;
+    if (grid > 2u * cus)
+        grid = 2u * cus;
+    if (r.op == AES_OP_CBC_ENC) {
+        grid = 1;
+        waves = 1;
+    }
     if (r.op == AES_OP_CBC_DEC)
-        hipLaunchKernelGGL((k_request<true, 2>), dim3(grid), dim3(64), 0, (hipStream_t)stream, r,
-                           tile, d_sched, n_sched, d_timg, d_in, d_out);
+        hipLaunchKernelGGL((k_request<true, 2>), dim3(grid), dim3(64 * waves), 0,
+                           (hipStream_t)stream, r, tile, d_sched, n_sched, d_timg, d_in, d_out);
     else
-        hipLaunchKernelGGL((k_request<false, 2>), dim3(grid), dim3(64), 0, (hipStream_t)stream, r,
-                           tile, d_sched, n_sched, d_timg, d_in, d_out);
+        hipLaunchKernelGGL((k_request<false, 2>), dim3(grid), dim3(64 * waves), 0,
+                           (hipStream_t)stream, r, tile, d_sched, n_sched, d_timg, d_in, d_out);
     return hipGetLastError();
 }
 

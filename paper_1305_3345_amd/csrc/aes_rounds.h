@@ -71,13 +71,13 @@ __device__ __forceinline__ uint32_t lds_word(const uint32_t *lds, uint32_t byte_
     return *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(lds) + byte_addr);
 }
 
-// Table T (0..3) looked up at byte K of v.  L is the lane constant of T's
-// 64 KiB region: byte 0 = (lane & 31) * 4, byte 2 = region.
+// Table T (0..3) looked up at byte K of v.  L0 = (lane & 31) * 4; tables 2
+// and 3 live in the second 64 KiB region (L0 | 0x10000, byte 2 = region).
 template <int K, int T>
-__device__ __forceinline__ uint32_t tlook(const uint32_t *lds, uint32_t v, uint32_t L0,
-                                          uint32_t L1) {
+__device__ __forceinline__ uint32_t tlook(const uint32_t *lds, uint32_t v, uint32_t L0) {
     // v_perm_b32 selector: byte0 <- L.byte0, byte1 <- v.byte K, byte2 <- L.byte2, byte3 <- 0
-    const uint32_t a = __builtin_amdgcn_perm(v, T < 2 ? L0 : L1, 0x0C020400u | ((4u + K) << 8));
+    const uint32_t L = T < 2 ? L0 : (L0 | 0x10000u);
+    const uint32_t a = __builtin_amdgcn_perm(v, L, 0x0C020400u | ((4u + K) << 8));
     return lds_word(lds, a + ((T & 1) ? 128u : 0u));
 }
 
@@ -95,61 +95,64 @@ __device__ __forceinline__ uint32_t pick_diag(uint32_t a, uint32_t b, uint32_t c
     return lo ^ hi;
 }
 
-// One full encryption round (SubBytes, ShiftRows, MixColumns, AddRoundKey).
+// One column of an encryption round:
+// Te0[a.b0] ^ Te1[b.b1] ^ Te2[c.b2] ^ Te3[d.b3] ^ k.
+__device__ __forceinline__ uint32_t round_col(const uint32_t *lds, uint32_t a, uint32_t b,
+                                              uint32_t c, uint32_t d, uint32_t k, uint32_t L0) {
+    return xor3(xor3(tlook<0, 0>(lds, a, L0), tlook<1, 1>(lds, b, L0), tlook<2, 2>(lds, c, L0)),
+                tlook<3, 3>(lds, d, L0), k);
+}
+
+// SubBytes of a.b0, b.b1, c.b2, d.b3 gathered into one word (a column of
+// the last round before AddRoundKey): Te_((r+3) mod 4) holds S(x) at byte r.
+__device__ __forceinline__ uint32_t sub_col(const uint32_t *lds, uint32_t a, uint32_t b,
+                                            uint32_t c, uint32_t d, uint32_t L0) {
+    return pick_diag(tlook<0, 3>(lds, a, L0), tlook<1, 0>(lds, b, L0), tlook<2, 1>(lds, c, L0),
+                     tlook<3, 2>(lds, d, L0));
+}
+
+// One full encryption round (SubBytes, ShiftRows, MixColumns, AddRoundKey):
+// column c takes row r from column c + r.
 __device__ __forceinline__ void enc_round(const uint32_t *lds, uint32_t s[4],
-                                          const uint32_t *__restrict__ rk, uint32_t L0,
-                                          uint32_t L1) {
-    const uint32_t t0 = xor3(xor3(tlook<0, 0>(lds, s[0], L0, L1), tlook<1, 1>(lds, s[1], L0, L1),
-                                  tlook<2, 2>(lds, s[2], L0, L1)),
-                             tlook<3, 3>(lds, s[3], L0, L1), rk[0]);
-    const uint32_t t1 = xor3(xor3(tlook<0, 0>(lds, s[1], L0, L1), tlook<1, 1>(lds, s[2], L0, L1),
-                                  tlook<2, 2>(lds, s[3], L0, L1)),
-                             tlook<3, 3>(lds, s[0], L0, L1), rk[1]);
-    const uint32_t t2 = xor3(xor3(tlook<0, 0>(lds, s[2], L0, L1), tlook<1, 1>(lds, s[3], L0, L1),
-                                  tlook<2, 2>(lds, s[0], L0, L1)),
-                             tlook<3, 3>(lds, s[1], L0, L1), rk[2]);
-    const uint32_t t3 = xor3(xor3(tlook<0, 0>(lds, s[3], L0, L1), tlook<1, 1>(lds, s[0], L0, L1),
-                                  tlook<2, 2>(lds, s[1], L0, L1)),
-                             tlook<3, 3>(lds, s[2], L0, L1), rk[3]);
+                                          const uint32_t *__restrict__ rk, uint32_t L0) {
+    const uint32_t t0 = round_col(lds, s[0], s[1], s[2], s[3], rk[0], L0);
+    const uint32_t t1 = round_col(lds, s[1], s[2], s[3], s[0], rk[1], L0);
+    const uint32_t t2 = round_col(lds, s[2], s[3], s[0], s[1], rk[2], L0);
+    const uint32_t t3 = round_col(lds, s[3], s[0], s[1], s[2], rk[3], L0);
     s[0] = t0;
     s[1] = t1;
     s[2] = t2;
     s[3] = t3;
 }
 
-// Last encryption round (no MixColumns): Te_((r+3) mod 4) holds S(x) at byte r.
+// Last encryption round (no MixColumns):
 // o_c = SubBytes/ShiftRows(s)_c ^ rk_c ^ x_c.
 __device__ __forceinline__ void enc_last(const uint32_t *lds, const uint32_t s[4],
                                          const uint32_t *__restrict__ rk, uint32_t L0,
-                                         uint32_t L1, const uint32_t x[4], uint32_t o[4]) {
+                                         const uint32_t x[4], uint32_t o[4]) {
 #pragma unroll
-    for (int c = 0; c < 4; c++) {
-        const uint32_t a = tlook<0, 3>(lds, s[c], L0, L1);
-        const uint32_t b = tlook<1, 0>(lds, s[(c + 1) & 3], L0, L1);
-        const uint32_t d2 = tlook<2, 1>(lds, s[(c + 2) & 3], L0, L1);
-        const uint32_t d3 = tlook<3, 2>(lds, s[(c + 3) & 3], L0, L1);
-        o[c] = xor3(pick_diag(a, b, d2, d3), rk[c], x[c]);
-    }
+    for (int c = 0; c < 4; c++)
+        o[c] = xor3(sub_col(lds, s[c], s[(c + 1) & 3], s[(c + 2) & 3], s[(c + 3) & 3], L0),
+                    rk[c], x[c]);
 }
 
 // One round of the equivalent inverse cipher (InvSubBytes, InvShiftRows,
 // InvMixColumns, AddRoundKey with the transformed key): row r of column c
 // comes from column c - r.
 __device__ __forceinline__ void dec_round(const uint32_t *lds, uint32_t s[4],
-                                          const uint32_t *__restrict__ dk, uint32_t L0,
-                                          uint32_t L1) {
-    const uint32_t t0 = xor3(xor3(tlook<0, 0>(lds, s[0], L0, L1), tlook<1, 1>(lds, s[3], L0, L1),
-                                  tlook<2, 2>(lds, s[2], L0, L1)),
-                             tlook<3, 3>(lds, s[1], L0, L1), dk[0]);
-    const uint32_t t1 = xor3(xor3(tlook<0, 0>(lds, s[1], L0, L1), tlook<1, 1>(lds, s[0], L0, L1),
-                                  tlook<2, 2>(lds, s[3], L0, L1)),
-                             tlook<3, 3>(lds, s[2], L0, L1), dk[1]);
-    const uint32_t t2 = xor3(xor3(tlook<0, 0>(lds, s[2], L0, L1), tlook<1, 1>(lds, s[1], L0, L1),
-                                  tlook<2, 2>(lds, s[0], L0, L1)),
-                             tlook<3, 3>(lds, s[3], L0, L1), dk[2]);
-    const uint32_t t3 = xor3(xor3(tlook<0, 0>(lds, s[3], L0, L1), tlook<1, 1>(lds, s[2], L0, L1),
-                                  tlook<2, 2>(lds, s[1], L0, L1)),
-                             tlook<3, 3>(lds, s[0], L0, L1), dk[3]);
+                                          const uint32_t *__restrict__ dk, uint32_t L0) {
+    const uint32_t t0 = xor3(xor3(tlook<0, 0>(lds, s[0], L0), tlook<1, 1>(lds, s[3], L0),
+                                  tlook<2, 2>(lds, s[2], L0)),
+                             tlook<3, 3>(lds, s[1], L0), dk[0]);
+    const uint32_t t1 = xor3(xor3(tlook<0, 0>(lds, s[1], L0), tlook<1, 1>(lds, s[0], L0),
+                                  tlook<2, 2>(lds, s[3], L0)),
+                             tlook<3, 3>(lds, s[2], L0), dk[1]);
+    const uint32_t t2 = xor3(xor3(tlook<0, 0>(lds, s[2], L0), tlook<1, 1>(lds, s[1], L0),
+                                  tlook<2, 2>(lds, s[0], L0)),
+                             tlook<3, 3>(lds, s[3], L0), dk[2]);
+    const uint32_t t3 = xor3(xor3(tlook<0, 0>(lds, s[3], L0), tlook<1, 1>(lds, s[2], L0),
+                                  tlook<2, 2>(lds, s[1], L0)),
+                             tlook<3, 3>(lds, s[0], L0), dk[3]);
     s[0] = t0;
     s[1] = t1;
     s[2] = t2;
@@ -206,7 +209,7 @@ __device__ __forceinline__ void store_block(uint8_t *dst, uint32_t b, uint32_t n
 
 // SP 800-38A 6.5: block b of the unit uses counter block nonce || BE64(ctr0 + b).
 template <int NB, int NR>
-__device__ __forceinline__ void ctr_unit(const uint32_t *lds, uint32_t L0, uint32_t L1,
+__device__ __forceinline__ void ctr_unit(const uint32_t *lds, uint32_t L0,
                                          uint32_t lane, const Unit &un,
                                          const uint32_t *__restrict__ rk, const uint8_t *in,
                                          uint8_t *out) {
@@ -233,12 +236,12 @@ __device__ __forceinline__ void ctr_unit(const uint32_t *lds, uint32_t L0, uint3
         for (int r = 1; r < NR; r++) {
 #pragma unroll
             for (int i = 0; i < NB; i++)
-                enc_round(lds, s[i], rk + 4 * r, L0, L1);
+                enc_round(lds, s[i], rk + 4 * r, L0);
         }
 #pragma unroll
         for (int i = 0; i < NB; i++) {
             uint32_t o[4];
-            enc_last(lds, s[i], rk + 4 * NR, L0, L1, x[i], o);
+            enc_last(lds, s[i], rk + 4 * NR, L0, x[i], o);
             store_block(dst, base + 64u * i + lane, nbytes, o);
         }
     }
@@ -246,7 +249,7 @@ __device__ __forceinline__ void ctr_unit(const uint32_t *lds, uint32_t L0, uint3
 
 // Key checks and round-count dispatch for one CTR unit (wave-uniform).
 template <int NB>
-__device__ __forceinline__ void run_ctr_unit(const uint32_t *lds, uint32_t L0, uint32_t L1,
+__device__ __forceinline__ void run_ctr_unit(const uint32_t *lds, uint32_t L0,
                                              uint32_t lane, const Unit &un,
                                              const aes_schedule_t *__restrict__ sched,
                                              uint32_t n_sched, const uint8_t *in, uint8_t *out) {
@@ -256,11 +259,11 @@ __device__ __forceinline__ void run_ctr_unit(const uint32_t *lds, uint32_t L0, u
     const aes_schedule_t *ks = sched + key;
     const uint32_t nr = ks->nr;
     if (nr == 10)
-        ctr_unit<NB, 10>(lds, L0, L1, lane, un, ks->ek, in, out);
+        ctr_unit<NB, 10>(lds, L0, lane, un, ks->ek, in, out);
     else if (nr == 12)
-        ctr_unit<NB, 12>(lds, L0, L1, lane, un, ks->ek, in, out);
+        ctr_unit<NB, 12>(lds, L0, lane, un, ks->ek, in, out);
     else if (nr == 14)
-        ctr_unit<NB, 14>(lds, L0, L1, lane, un, ks->ek, in, out);
+        ctr_unit<NB, 14>(lds, L0, lane, un, ks->ek, in, out);
 }
 
 // ------------------------------------------------------- CBC-decrypt tiles
@@ -274,7 +277,7 @@ __device__ __forceinline__ uint32_t shift_up(uint32_t old, uint32_t v) {
 // 64i + l; its predecessor is lane l-1's ciphertext, and lane 0 takes lane 63
 // of the previous step (or the block before the unit).
 template <int NB, int NR>
-__device__ __forceinline__ void cbcdec_unit(const uint32_t *lds, uint32_t L0, uint32_t L1,
+__device__ __forceinline__ void cbcdec_unit(const uint32_t *lds, uint32_t L0,
                                             uint32_t L2, uint32_t lane, const Unit &un,
                                             const uint4 *snap, const uint32_t *__restrict__ dk,
                                             const uint8_t *in, uint8_t *out) {
@@ -317,7 +320,7 @@ __device__ __forceinline__ void cbcdec_unit(const uint32_t *lds, uint32_t L0, ui
         for (int r = 1; r < NR; r++) {
 #pragma unroll
             for (int i = 0; i < NB; i++)
-                dec_round(lds, s[i], dk + 4 * r, L0, L1);
+                dec_round(lds, s[i], dk + 4 * r, L0);
         }
 #pragma unroll
         for (int i = 0; i < NB; i++) {
@@ -329,7 +332,7 @@ __device__ __forceinline__ void cbcdec_unit(const uint32_t *lds, uint32_t L0, ui
 }
 
 template <int NB>
-__device__ __forceinline__ void run_dec_unit(const uint32_t *lds, uint32_t L0, uint32_t L1,
+__device__ __forceinline__ void run_dec_unit(const uint32_t *lds, uint32_t L0,
                                              uint32_t L2, uint32_t lane, const Unit &un,
                                              const uint4 *snap,
                                              const aes_schedule_t *__restrict__ sched,
@@ -340,11 +343,11 @@ __device__ __forceinline__ void run_dec_unit(const uint32_t *lds, uint32_t L0, u
     const aes_schedule_t *ks = sched + key;
     const uint32_t nr = ks->nr;
     if (nr == 10)
-        cbcdec_unit<NB, 10>(lds, L0, L1, L2, lane, un, snap, ks->dk, in, out);
+        cbcdec_unit<NB, 10>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
     else if (nr == 12)
-        cbcdec_unit<NB, 12>(lds, L0, L1, L2, lane, un, snap, ks->dk, in, out);
+        cbcdec_unit<NB, 12>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
     else if (nr == 14)
-        cbcdec_unit<NB, 14>(lds, L0, L1, L2, lane, un, snap, ks->dk, in, out);
+        cbcdec_unit<NB, 14>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
 }
 
 // ------------------------------------------------------- CBC-encrypt chains
@@ -355,7 +358,7 @@ __device__ __forceinline__ void run_dec_unit(const uint32_t *lds, uint32_t L0, u
 // wave) and a lane with fewer rounds sits out the extra ones, so mixed waves
 // cost MAXNR rounds per block rather than the sum over key sizes.
 template <int MAXNR>
-__device__ __forceinline__ void chain_run(const uint32_t *lds, uint32_t L0, uint32_t L1,
+__device__ __forceinline__ void chain_run(const uint32_t *lds, uint32_t L0,
                                           const Unit &un, const uint32_t *ek, uint32_t nr,
                                           const uint8_t *in, uint8_t *out) {
     uint32_t rk[4 * (MAXNR + 1)];
@@ -398,10 +401,10 @@ __device__ __forceinline__ void chain_run(const uint32_t *lds, uint32_t L0, uint
 #pragma unroll
                 for (int r = 1; r < MAXNR; r++) {
                     if (r < 10 || (uint32_t)r < nr)
-                        enc_round(lds, s, rk + 4 * r, L0, L1);
+                        enc_round(lds, s, rk + 4 * r, L0);
                 }
                 const uint32_t zero[4] = {0u, 0u, 0u, 0u};
-                enc_last(lds, s, rkl, L0, L1, zero, prev);
+                enc_last(lds, s, rkl, L0, zero, prev);
                 *reinterpret_cast<uint4 *>(dst + ((b + j) << 4)) =
                     make_uint4(prev[0], prev[1], prev[2], prev[3]);
             }
@@ -411,7 +414,7 @@ __device__ __forceinline__ void chain_run(const uint32_t *lds, uint32_t L0, uint
 
 // One chain per lane; lanes of one wave may have different keys and lengths.
 // A lane whose schedule is invalid (bad index or round count) does nothing.
-__device__ __forceinline__ void run_chain(const uint32_t *lds, uint32_t L0, uint32_t L1,
+__device__ __forceinline__ void run_chain(const uint32_t *lds, uint32_t L0,
                                           const Unit &un, const aes_schedule_t *__restrict__ sched,
                                           uint32_t n_sched, const uint8_t *in, uint8_t *out) {
     const uint32_t key = un.meta & META_KEY_MASK;
@@ -423,17 +426,17 @@ __device__ __forceinline__ void run_chain(const uint32_t *lds, uint32_t L0, uint
     if (!ok)
         return;
     if (m14)
-        chain_run<14>(lds, L0, L1, un, ks->ek, nr, in, out);
+        chain_run<14>(lds, L0, un, ks->ek, nr, in, out);
     else if (m12)
-        chain_run<12>(lds, L0, L1, un, ks->ek, nr, in, out);
+        chain_run<12>(lds, L0, un, ks->ek, nr, in, out);
     else
-        chain_run<10>(lds, L0, L1, un, ks->ek, nr, in, out);
+        chain_run<10>(lds, L0, un, ks->ek, nr, in, out);
 }
 
 // Chains of a wave: `cl` active lanes per wave (spreading few chains over more
 // waves and compute units lowers nothing but the per-CU contention; each lane
 // is still one serial chain).  Wave e takes chains e*cl + lane, then strides.
-__device__ __forceinline__ void chain_loop(const uint32_t *lds, uint32_t L0, uint32_t L1,
+__device__ __forceinline__ void chain_loop(const uint32_t *lds, uint32_t L0,
                                            uint32_t lane, uint32_t e, uint32_t n_waves,
                                            uint32_t cl, const Unit *__restrict__ chains,
                                            uint32_t n_chain,
@@ -443,7 +446,138 @@ __device__ __forceinline__ void chain_loop(const uint32_t *lds, uint32_t L0, uin
         return;
     for (uint64_t c = (uint64_t)e * cl + lane; c < n_chain; c += (uint64_t)n_waves * cl) {
         const Unit un = chains[c];
-        run_chain(lds, L0, L1, un, sched, n_sched, in, out);
+        run_chain(lds, L0, un, sched, n_sched, in, out);
+    }
+}
+
+// ------------------------------------------------ one chain on four lanes
+//
+// A single serial chain (the per-request launch and the serving engine)
+// runs on lanes 0..3: lane q holds state column q, reads the other three
+// columns from its quad neighbours with DPP quad_perm and does its column's
+// four lookups, so a round costs four dependent LDS reads per lane instead of
+// sixteen.  Round keys: word q of each round key in VGPRs.
+
+// Lane q of each quad receives lane (q + K) mod 4's v.
+template <int K>
+__device__ __forceinline__ uint32_t quad_next(uint32_t v) {
+    // quad_perm selectors [1,2,3,0], [2,3,0,1], [3,0,1,2]
+    constexpr int sel = K == 1 ? 0x39 : (K == 2 ? 0x4E : 0x93);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, sel, 0xF, 0xF, false);
+}
+
+// Runs a quad's chain.  Lanes of a quad share one chain (un, ek, nr); quads
+// of a wave may have different chains, keys and key sizes: rounds run up to
+// MAXNR, a quad with fewer rounds sits out the extra ones.
+template <int MAXNR>
+__device__ __forceinline__ void chain_quad_run(const uint32_t *lds, uint32_t L0, uint32_t q,
+                                               const Unit &un, const uint32_t *ek, uint32_t nr,
+                                               const uint8_t *in, uint8_t *out) {
+    uint32_t rk[MAXNR + 1];
+#pragma unroll
+    for (int r = 0; r <= MAXNR; r++)
+        rk[r] = ek[4 * r + q];
+    const uint32_t rkl = nr == 10 ? rk[10] : (nr == 12 && MAXNR >= 12 ? rk[12] : rk[MAXNR]);
+    // the IV's word q, selected with masks (an indexed read of un.w would
+    // put the record in scratch memory)
+    uint32_t prev = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < 4; w++)
+        prev |= un.w[w] & (0u - (uint32_t)(q == w));
+    const uint32_t nblk = un.nbytes >> 4;
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(in + un.off) + q;
+    uint32_t *dst = reinterpret_cast<uint32_t *>(out + un.off) + q;
+    constexpr uint32_t PF = 8;  // blocks fetched together
+    for (uint32_t b = 0; b < nblk; b += PF) {
+        uint32_t x[PF];
+#pragma unroll
+        for (uint32_t j = 0; j < PF; j++)
+            x[j] = b + j < nblk ? src[4 * (b + j)] : 0u;
+#pragma unroll
+        for (uint32_t j = 0; j < PF; j++) {
+            if (b + j < nblk) {
+                uint32_t st = x[j] ^ prev ^ rk[0];
+#pragma unroll
+                for (int r = 1; r < MAXNR; r++) {
+                    if (r < 10 || (uint32_t)r < nr)
+                        st = round_col(lds, st, quad_next<1>(st), quad_next<2>(st),
+                                       quad_next<3>(st), rk[r], L0);
+                }
+                prev = sub_col(lds, st, quad_next<1>(st), quad_next<2>(st), quad_next<3>(st), L0) ^
+                       rkl;
+                dst[4 * (b + j)] = prev;
+            }
+        }
+    }
+}
+
+// Key check and round-count dispatch for the chains of a wave's quads (un,
+// per quad); MAXNR is the largest round count among them.
+__device__ __forceinline__ void run_chains_quad(const uint32_t *lds, uint32_t L0, uint32_t q,
+                                                bool active, const Unit &un,
+                                                const aes_schedule_t *__restrict__ sched,
+                                                uint32_t n_sched, const uint8_t *in,
+                                                uint8_t *out) {
+    const uint32_t key = un.meta & META_KEY_MASK;
+    const bool keyed = active && key < n_sched;
+    const aes_schedule_t *ks = sched + (keyed ? key : 0u);
+    const uint32_t nr = keyed ? ks->nr : 0u;
+    const bool ok = nr == 10 || nr == 12 || nr == 14;
+    const uint64_t m12 = __ballot(ok && nr == 12);
+    const uint64_t m14 = __ballot(ok && nr == 14);
+    if (!ok)
+        return;
+    if (m14)
+        chain_quad_run<14>(lds, L0, q, un, ks->ek, nr, in, out);
+    else if (m12)
+        chain_quad_run<12>(lds, L0, q, un, ks->ek, nr, in, out);
+    else
+        chain_quad_run<10>(lds, L0, q, un, ks->ek, nr, in, out);
+}
+
+// Runs one CBC-encrypt chain on lanes 0..3 of the calling wave (the other
+// lanes take no part).  Key and round count are wave-uniform.
+__device__ __forceinline__ void run_chain_quad(const uint32_t *lds, uint32_t L0, uint32_t lane,
+                                               const Unit &un,
+                                               const aes_schedule_t *__restrict__ sched,
+                                               uint32_t n_sched, const uint8_t *in,
+                                               uint8_t *out) {
+    const uint32_t key = un.meta & META_KEY_MASK;
+    if (key >= n_sched || lane >= 4u)
+        return;
+    const aes_schedule_t *ks = sched + key;
+    const uint32_t nr = ks->nr;
+    if (nr == 10)
+        chain_quad_run<10>(lds, L0, lane, un, ks->ek, nr, in, out);
+    else if (nr == 12)
+        chain_quad_run<12>(lds, L0, lane, un, ks->ek, nr, in, out);
+    else if (nr == 14)
+        chain_quad_run<14>(lds, L0, lane, un, ks->ek, nr, in, out);
+}
+
+// Chains of a wave in quads: 16 chains per wave, four lanes each.  Wave e
+// takes chains 16 e + lane / 4, then strides by 16 n_waves.
+__device__ __forceinline__ void chain_loop_quad(const uint32_t *lds, uint32_t L0,
+                                                uint32_t lane, uint32_t e, uint32_t n_waves,
+                                                const Unit *__restrict__ chains,
+                                                uint32_t n_chain,
+                                                const aes_schedule_t *__restrict__ sched,
+                                                uint32_t n_sched, const uint8_t *in,
+                                                uint8_t *out) {
+    const uint32_t q = lane & 3u;
+    for (uint64_t base = (uint64_t)e * 16u; base < n_chain; base += (uint64_t)n_waves * 16u) {
+        const uint64_t c = base + (lane >> 2);
+        const bool active = c < n_chain;
+        Unit un;
+        if (active) {
+            un = chains[c];
+        } else {
+            un.off = 0;
+            un.nbytes = 0;
+            un.meta = 0;
+            un.w[0] = un.w[1] = un.w[2] = un.w[3] = 0u;
+        }
+        run_chains_quad(lds, L0, q, active, un, sched, n_sched, in, out);
     }
 }
 

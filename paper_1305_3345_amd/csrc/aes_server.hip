@@ -306,7 +306,6 @@ template <bool DEC>
 __device__ void worker_loop(const ServeArgs &a, const uint32_t *lds) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t L0 = (lane & 31u) << 2;
-    const uint32_t L1 = L0 | 0x10000u;
     const uint32_t L2 = L0 | SI_BASE;
     const int qi = DEC ? 1 : 0;
     uint64_t idx;
@@ -326,14 +325,12 @@ __device__ void worker_loop(const ServeArgs &a, const uint32_t *lds) {
         const uint32_t slot = __hip_atomic_load(&p->slot, __ATOMIC_RELAXED, AGT);
         const uint32_t op = (un.meta >> META_OP_SHIFT) & 3u;
         if (DEC) {
-            run_dec_unit<1>(lds, L0, L1, L2, lane, un, nullptr, a.keys, a.n_keys, src, dst);
+            run_dec_unit<1>(lds, L0, L2, lane, un, nullptr, a.keys, a.n_keys, src, dst);
         } else if (op == AES_OP_CBC_ENC) {
-            // One chain: every lane runs it in lockstep (same result, same
-            // stores), which costs the time of one lane and keeps the wave's
-            // control flow uniform.
-            run_chain(lds, L0, L1, un, a.keys, a.n_keys, src, dst);
+            // One serial chain, on four lanes (one state column each).
+            run_chain_quad(lds, L0, lane, un, a.keys, a.n_keys, src, dst);
         } else {
-            run_ctr_unit<1>(lds, L0, L1, lane, un, a.keys, a.n_keys, src, dst);
+            run_ctr_unit<1>(lds, L0, lane, un, a.keys, a.n_keys, src, dst);
         }
         // Make this unit's output visible beyond the device, then count it.
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");

@@ -42,8 +42,9 @@ bool tile_shape_supported(int nb, int wg_threads);
 
 struct ChainLaunch {
     int wg_threads = 256;
-    int lanes = 64;  // active lanes (chains) per wave
-    int grid = 0;    // 0 = as many as the chains need, at most one per compute unit
+    int lanes = 64;     // active lanes (chains) per wave, one lane per chain
+    bool quad = false;  // instead: 16 chains per wave on four lanes each
+    int grid = 0;       // 0 = as many as the chains need, at most one per compute unit
 };
 
 // Arguments of the fused mixed-batch kernel (one launch for all three ops).
@@ -59,7 +60,8 @@ struct MixedArgs {
     uint32_t n_dec, n_ctr, n_chain;
     uint32_t n_sched;
     uint32_t n_dec_wg;      // workgroups [0, n_dec_wg) hold the decryption tables
-    uint32_t chain_lanes;   // active lanes per chain wave
+    uint32_t chain_lanes;   // active lanes per chain wave (one lane per chain)
+    uint32_t chain_quad;    // 1: 16 chains per wave on four lanes each
 };
 
 // Host-side launchers (aes_kernels.hip).  Each returns a hipError_t value.

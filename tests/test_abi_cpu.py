@@ -261,7 +261,8 @@ def test_launch_config_validation(ag, hctx):
     hctx.set_config(ctr_variant=ag.AES_CTR_BITSLICE, tile_bytes=8192)
     got = hctx.get_config()
     assert got["ctr_variant"] == ag.AES_CTR_BITSLICE and got["tile_bytes"] == 8192
-    for bad in ({"ctr_variant": 2}, {"tile_bytes": 1000}, {"ctr_nb": 3}, {"chain_lanes": 0},
+    for bad in ({"ctr_variant": 2}, {"chain_quad": 2}, {"tile_bytes": 1000}, {"ctr_nb": 3},
+                {"chain_lanes": 0},
                 {"mixed_nb": 4}, {"fuse": 2}):
         with pytest.raises(ag.AesError) as e:
             hctx.set_config(**bad)

@@ -47,12 +47,29 @@ def mixed_workload(n=300, max_pages=12, three_sizes=True):
 @pytest.mark.parametrize("chain_lanes", [16, 64])
 def test_mixed_batch_fused_and_split(fresh, fuse, mixed_nb, chain_lanes):
     print(f"[gpu] mixed fuse={fuse} nb={mixed_nb} lanes={chain_lanes}", flush=True)
-    fresh.set_config(fuse=fuse, mixed_nb=mixed_nb, chain_lanes=chain_lanes)
+    fresh.set_config(fuse=fuse, mixed_nb=mixed_nb, chain_lanes=chain_lanes, chain_quad=0)
     wl = mixed_workload()
     inp = wl.data()
     want = run_oracle(wl, inp)
     for form in ("batch", "plan"):
         check(run_gpu(fresh, wl, inp, form=form), want, f"mixed {form}")
+
+
+@pytest.mark.parametrize("fuse", [1, 0])
+def test_chains_on_four_lanes(fresh, fuse):
+    """CBC-encrypt chains 16 per wave on four lanes each (chain_quad = 1):
+    uneven chains of all three key sizes, alone and inside a mixed batch."""
+    print(f"[gpu] four-lane chains, fuse={fuse}", flush=True)
+    fresh.set_config(chain_quad=1, fuse=fuse)
+    wl = mixed_workload()
+    inp = wl.data()
+    want = run_oracle(wl, inp)
+    for form in ("batch", "plan"):
+        check(run_gpu(fresh, wl, inp, form=form), want, f"mixed {form}")
+    enc = wl.reqs[wl.reqs["op"] == workloads.OP_CBC_ENC][:37]
+    check(run_gpu(fresh, wl, inp, reqs=enc), run_oracle(wl, inp, reqs=enc), "chains only")
+    check(run_gpu(fresh, wl, inp, reqs=enc, inplace=True),
+          run_oracle(wl, inp, reqs=enc, inplace=True), "chains in place")
 
 
 @pytest.mark.parametrize("ops", [(0, 1), (0, 2), (1, 2), (0,), (1,), (2,)])

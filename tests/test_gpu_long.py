@@ -4,9 +4,9 @@ encryption of 4,096 chains of 1 MiB.
 
 The oracle computes sampled spans (CTR keystream is seekable: the span at
 byte a of a chunk uses counter ctr0 + a / 16) and whole sampled chains;
-properties cover every byte: the chunked batch equals one 8 GiB request,
-CTR applied twice restores the input, and CBC decryption of the chains'
-output restores their input."""
+properties cover every byte: the chunked batch equals the same stream cut
+into 3 + 3 + 2 GiB requests, CTR applied twice restores the input, and CBC
+decryption of the chains' output restores their input."""
 import numpy as np
 import pytest
 import torch
@@ -64,16 +64,24 @@ def test_ctr_8gib_continuous_stream(ctx):
             got = d_out[o + start:o + start + n].cpu().numpy()
             msg = first_mismatch(got, ctr_span_oracle(wl, r, start, n, src))
             assert msg is None, f"chunk {ci} at {start}: {msg}"
-    # one 8 GiB request: the same counter stream, so the same bytes
-    one = wl.reqs[:1].copy()
-    one["length"] = nbytes
-    d_one = torch.empty_like(d_in)
-    plan = a.Plan(ctx, one, 1, nbytes)
-    plan.launch(d_s, d_in, d_one)
+    # the same stream cut differently (requests are limited to < 4 GiB):
+    # 3 + 3 + 2 GiB with the counter continuing across them
+    cuts = [0, 3 << 30, 6 << 30, nbytes]
+    big = np.zeros(3, workloads.REQ_DTYPE)
+    for i in range(3):
+        big["offset"][i] = cuts[i]
+        big["length"][i] = cuts[i + 1] - cuts[i]
+        iv = wl.reqs["iv"][0].copy()
+        iv[8:] = np.frombuffer((cuts[i] // 16).to_bytes(8, "big"), np.uint8)
+        big["iv"][i] = iv
+    big["op"] = workloads.OP_CTR
+    d_big = torch.empty_like(d_in)
+    plan = a.Plan(ctx, big, 1, nbytes)
+    plan.launch(d_s, d_in, d_big)
     torch.cuda.synchronize()
     plan.close()
-    assert torch.equal(d_one, d_out), "chunked batch differs from one 8 GiB request"
-    del d_one
+    assert torch.equal(d_big, d_out), "chunked batch differs from 3 + 3 + 2 GiB requests"
+    del d_big
     # CTR twice restores the input
     back = torch.empty_like(d_in)
     plan = a.Plan(ctx, wl.reqs, 1, nbytes)
