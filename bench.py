@@ -82,6 +82,28 @@ def cpu_baseline(sample_pages: int):
                       f"({total >> 20} MiB), same keys/IVs/bytes, {secs:.1f} s"}
 
 
+def profiled_traffic(kernel: str, pages: int):
+    """HBM bytes per launch of `kernel` on the 65,536-page workload, from the
+    committed rocprofv3 counter summary -- or None when the kernel sources
+    have changed since the counters were taken (their SHA-1 is recorded in
+    the summary) or the workload differs."""
+    import hashlib
+    import re
+
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "tile_kernels_config2_counters.md")
+    if pages != 65536 or not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"SHA-1 of `aes_rounds.h` \+ `aes_kernels.hip`\): `([0-9a-f]{40})`", text)
+    src = b"".join(open(os.path.join(here, "paper_1305_3345_amd", "csrc", f), "rb").read()
+                   for f in ("aes_rounds.h", "aes_kernels.hip"))
+    if not m or hashlib.sha1(src).hexdigest() != m.group(1):
+        return None
+    m = re.search(r"- `" + re.escape(kernel) + r"`: (\d+)", text)
+    return int(m.group(1)) if m else None
+
+
 def time_gpu(fn, iters, stream):
     """Median milliseconds of fn() over iters runs after one warm-up (HIP events)."""
     import torch
@@ -405,7 +427,8 @@ def main():
     algo_per_launch = d["algo_bytes"] / d["launches"]
     achieved = algo_per_launch / avg_ms / 1e6
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": profiled_traffic(f"aesgpu::{dom}", n_pages),
                 "kernel": f"aesgpu::{dom}", "avg_launch_ms": round(avg_ms, 4),
                 "algo_bytes_per_launch": int(algo_per_launch)}
 

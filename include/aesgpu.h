@@ -174,7 +174,7 @@ typedef struct aes_plan aes_plan_t;
  *      CBC -- the IV as four little-endian words (first unit of a request).
  * CTR and CBC-decryption requests become tiles of the context's tile size
  * (4096 bytes by default); each CBC-encryption request is one unit (a serial
- * chain), and chains are ordered longest first. */
+ * chain), and chains are grouped by key, longest first within a key. */
 typedef struct aes_unit {
     uint64_t offset;
     uint32_t nbytes;
@@ -204,8 +204,9 @@ int aes_plan_create(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint
 int aes_plan_launch(aes_plan_t *plan, const aes_schedule_t *d_scheds, const uint8_t *d_in,
                     uint8_t *d_out, void *stream);
 int aes_plan_info(const aes_plan_t *plan, aes_plan_info_t *info);
-/* Copies up to max unit records (CBC-decrypt tiles, then CTR tiles, then
- * chains) to out and sets *n_out to the plan's total unit count. */
+/* Copies up to max unit records (CBC-decrypt tiles, then CTR tiles grouped by
+ * key, then chains grouped by key, longest first within a key) to out and
+ * sets *n_out to the plan's total unit count. */
 int aes_plan_units(const aes_plan_t *plan, aes_unit_t *out, uint64_t max, uint64_t *n_out);
 /* Waits for the device to be idle, then frees the plan.  NULL is a no-op. */
 void aes_plan_destroy(aes_plan_t *plan);

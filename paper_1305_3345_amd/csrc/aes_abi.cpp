@@ -131,7 +131,7 @@ inline uint64_t be64(const uint8_t *p) {
 struct Planned {
     std::vector<Unit> dec;     // CBC-decrypt tiles
     std::vector<Unit> ctr;     // CTR tiles
-    std::vector<Unit> chains;  // CBC-encrypt chains, longest first
+    std::vector<Unit> chains;  // CBC-encrypt chains, by key, longest first within a key
     uint64_t payload = 0;
     uint64_t extent = 0;
     uint64_t dec_bytes = 0, ctr_bytes = 0, chain_bytes = 0;
@@ -207,10 +207,14 @@ int plan_units(const aes_req_t *reqs, uint64_t n, uint32_t tile_bytes, Planned &
         std::stable_sort(p.ctr.begin(), p.ctr.end(), [](const Unit &a, const Unit &b) {
             return (a.meta & META_KEY_MASK) < (b.meta & META_KEY_MASK);
         });
-        // Longest chain first: a chain's lane finishes last, so the longest
-        // ones start first and neighbouring lanes get similar lengths.
-        std::stable_sort(p.chains.begin(), p.chains.end(),
-                         [](const Unit &a, const Unit &b) { return a.nbytes > b.nbytes; });
+        // Chains grouped by key, longest first within a key: a wave runs the
+        // largest round count among its chains for all of them, so chains
+        // that share a key (and so a key size) share waves; and longer
+        // chains start first.
+        std::stable_sort(p.chains.begin(), p.chains.end(), [](const Unit &a, const Unit &b) {
+            const uint32_t ka = a.meta & META_KEY_MASK, kb = b.meta & META_KEY_MASK;
+            return ka != kb ? ka < kb : a.nbytes > b.nbytes;
+        });
     } catch (const std::bad_alloc &) {
         return AES_ERR_NOMEM;
     }

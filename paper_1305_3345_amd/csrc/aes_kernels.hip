@@ -71,7 +71,7 @@ __global__ __launch_bounds__(1024) void k_chains(const Unit *__restrict__ chains
 // decryption tables and work the CBC-decrypt tiles; the others hold the
 // encryption tables, start the CBC-encrypt chains (the long serial work)
 // on their first waves, and every encryption wave then works CTR tiles.
-template <int NB>
+template <int NB, bool QUAD>
 __global__ __launch_bounds__(1024) void k_mixed(MixedArgs a) {
     __shared__ uint32_t lds[LDS_DEC_WORDS];
     const uint32_t lane = threadIdx.x & 63u;
@@ -95,20 +95,28 @@ __global__ __launch_bounds__(1024) void k_mixed(MixedArgs a) {
     const uint32_t n_enc_wg = gridDim.x - a.n_dec_wg;
     const uint32_t e = spread_wave(blockIdx.x - a.n_dec_wg, n_enc_wg);
     const uint32_t nw = __builtin_amdgcn_readfirstlane(n_enc_wg * wpb);
+    // Waves [0, cw) run the chains and stop; the others work the CTR tiles
+    // (at least half of the waves when there are any), so the two paths
+    // share no registers.
+    uint32_t cw = 0;
     if (a.n_chain) {
-        const uint32_t per_wave = a.chain_quad ? 16u : a.chain_lanes;
+        const uint32_t per_wave = QUAD ? 16u : a.chain_lanes;
         const uint32_t chain_waves = (uint32_t)(((uint64_t)a.n_chain + per_wave - 1) / per_wave);
-        const uint32_t cw = chain_waves < nw ? chain_waves : nw;
+        const uint32_t cap = a.n_ctr ? nw / 2u : nw;
+        cw = chain_waves < cap ? chain_waves : cap;
+        if (cw < 1u)
+            cw = 1u;
         if (e < cw) {
-            if (a.chain_quad)
+            if (QUAD)
                 chain_loop_quad(lds, L0, lane, e, cw, a.chains, a.n_chain, a.sched, a.n_sched,
                                 a.in, a.out);
             else
                 chain_loop(lds, L0, lane, e, cw, a.chain_lanes, a.chains, a.n_chain, a.sched,
                            a.n_sched, a.in, a.out);
+            return;
         }
     }
-    for (uint32_t u = e; u < a.n_ctr; u += nw) {
+    for (uint32_t u = e - cw; u < a.n_ctr; u += nw - cw) {
         const Unit un = a.ctr[u];
         run_ctr_unit<NB>(lds, L0, lane, un, a.sched, a.n_sched, a.in, a.out);
     }
@@ -286,7 +294,11 @@ int launch_cbcenc_chains(const Unit *d_units, uint32_t n_units, const aes_schedu
 int launch_mixed(const MixedArgs &a, int nb, int grid, void *stream) {
     if (!a.n_dec && !a.n_ctr && !a.n_chain)
         return hipSuccess;
-    void (*k)(MixedArgs) = nb == 1 ? &k_mixed<1> : (nb == 2 ? &k_mixed<2> : nullptr);
+    void (*k)(MixedArgs) = nullptr;
+    if (nb == 1)
+        k = a.chain_quad ? &k_mixed<1, true> : &k_mixed<1, false>;
+    else if (nb == 2)
+        k = a.chain_quad ? &k_mixed<2, true> : &k_mixed<2, false>;
     if (!k || grid < 1 || (a.n_dec && a.n_dec_wg < 1) ||
         ((a.n_ctr || a.n_chain) && (uint32_t)grid <= a.n_dec_wg) || a.chain_lanes < 1 ||
         a.chain_lanes > 64 || a.chain_quad > 1)

@@ -202,12 +202,15 @@ def _check_plan(ag, plan, reqs, tile):
             total += n
     assert total == info["payload_bytes"]
     assert len(units) == info["n_units_cbc_dec"] + info["n_units_ctr"] + info["n_chains_cbc_enc"]
-    # order: CBC-dec tiles, CTR tiles, then chains longest first
+    # order: CBC-dec tiles, CTR tiles, then chains
     k = info["n_units_cbc_dec"]
     assert (op_of[:k] == ag.AES_OP_CBC_DEC).all()
     assert (op_of[k:k + info["n_units_ctr"]] == ag.AES_OP_CTR).all()
     ch = units[k + info["n_units_ctr"]:]
-    assert (np.diff(ch["nbytes"].astype(np.int64)) <= 0).all()
+    ch_key = (ch["meta"] & 0xFFFFFF).astype(np.int64)
+    assert (np.diff(ch_key) >= 0).all()  # chains grouped by key ...
+    for key in np.unique(ch_key):  # ... longest first within a key
+        assert (np.diff(ch["nbytes"][ch_key == key].astype(np.int64)) <= 0).all()
     # CTR tiles grouped by key, request order kept within a key
     ctr = units[k:k + info["n_units_ctr"]]
     key_of = (ctr["meta"] & 0xFFFFFF).astype(np.int64)
