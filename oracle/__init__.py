@@ -19,6 +19,8 @@ from . import build as _build
 OP_CBC_ENC = 0
 OP_CBC_DEC = 1
 OP_CTR = 2
+OP_ECB_ENC = 3
+OP_ECB_DEC = 4
 
 # Request record of the batch driver (layout of oracle_req_t in aes_oracle.c).
 REQ_DTYPE = np.dtype([("offset", "<u8"), ("length", "<u8"), ("key_idx", "<u4"),
@@ -99,9 +101,10 @@ def ecb(key, key_bits: int, data, decrypt: bool = False) -> np.ndarray:
 
 
 def mode(op: int, key, key_bits: int, iv, data) -> np.ndarray:
-    """One CBC-encrypt / CBC-decrypt / CTR request over a contiguous buffer."""
+    """One CBC-encrypt / CBC-decrypt / CTR / ECB-encrypt / ECB-decrypt request
+    over a contiguous buffer (ECB takes no IV: iv may be None)."""
     k = _u8(key)
-    v = _u8(iv)
+    v = _u8(np.zeros(16, np.uint8) if iv is None else iv)
     d = _u8(data)
     out = np.empty_like(d)
     st = _load().oracle_mode(op, _ptr(k), key_bits, _ptr(v), _ptr(d), _ptr(out), d.size)

@@ -14,7 +14,8 @@
  *     section 5.1 (Cipher), section 5.2 (KeyExpansion),
  *     section 5.3 (InvCipher, the straightforward form -- not the equivalent
  *     inverse cipher the GPU kernels use).
- *   - NIST SP 800-38A section 6.2 (CBC) and section 6.5 with appendix B.1
+ *   - NIST SP 800-38A section 6.1 (ECB), section 6.2 (CBC) and section 6.5
+ *     with appendix B.1
  *     (CTR, counter incremented on the low m = 64 bits, big-endian, mod 2^64,
  *     no carry into the high 64 bits; a final partial block uses the leading
  *     bytes of the last keystream block).
@@ -40,6 +41,8 @@
 #define OP_CBC_ENC 0
 #define OP_CBC_DEC 1
 #define OP_CTR 2
+#define OP_ECB_ENC 3
+#define OP_ECB_DEC 4
 
 /* One request of a batch: bytes [offset, offset+length) of the input buffer
  * are transformed into the same byte range of the output buffer. */
@@ -379,6 +382,20 @@ int oracle_mode(uint32_t op, const uint8_t *key, uint32_t key_bits, const uint8_
     case OP_CTR:
         ctr_xcrypt(in, out, len, iv, w, nr);
         return ORACLE_OK;
+    case OP_ECB_ENC:
+    case OP_ECB_DEC:
+        /* SP 800-38A 6.1: every block on its own, no IV */
+        if (len % 16)
+            return ORACLE_ERR_LENGTH;
+        for (uint64_t j = 0; j < len; j += 16) {
+            uint8_t x[16];
+            if (op == OP_ECB_DEC)
+                inv_cipher(in + j, x, w, nr);
+            else
+                cipher(in + j, x, w, nr);
+            memcpy(out + j, x, 16);
+        }
+        return ORACLE_OK;
     default:
         return ORACLE_ERR_ARG;
     }
@@ -432,7 +449,7 @@ int oracle_batch(const uint8_t *in, uint8_t *out, uint64_t buf_bytes, const orac
     init();
     for (uint64_t i = 0; i < n_reqs; i++) {
         const oracle_req_t *r = &reqs[i];
-        if (r->key_idx >= n_keys || r->op > OP_CTR)
+        if (r->key_idx >= n_keys || r->op > OP_ECB_DEC)
             return ORACLE_ERR_ARG;
         if (rounds_for(key_bits[r->key_idx]) < 0)
             return ORACLE_ERR_KEYSIZE;

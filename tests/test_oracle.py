@@ -9,6 +9,8 @@
   decryption equals the block-parallel form D(C_j) xor C_(j-1), CTR is an
   involution and its keystream is E(T_1) || E(T_2) || ..., and the 64-bit
   counter wraps without touching the nonce half.
+* ECB requests (ops 3 and 4) against OpenSSL's EVP ECB, block-position
+  independence, whole-block lengths.
 * Batch semantics: bytes outside every request keep their sentinel value and
   each request equals the same request run alone.
 """
@@ -82,6 +84,27 @@ def test_ecb_matches_openssl(bits):
         back = oracle.ecb(key[: bits // 8], bits, ours, decrypt=True)
         assert np.array_equal(back, data)
         assert np.array_equal(openssl_ref.ecb(bits, key, ours, decrypt=True), data)
+
+
+@pytest.mark.parametrize("bits", KEY_BITS)
+def test_ecb_mode_requests_match_openssl(bits):
+    """The ECB request ops (3 = encrypt, 4 = decrypt) of the mode and batch
+    entry points, against OpenSSL's EVP ECB (SP 800-38A 6.1)."""
+    r = rng(50 + bits)
+    for nblk in (0, 1, 3, 256, 1000):
+        key = r.integers(0, 256, 32, dtype=np.uint8)
+        data = r.integers(0, 256, 16 * nblk, dtype=np.uint8)
+        enc = oracle.mode(oracle.OP_ECB_ENC, key[: bits // 8], bits, None, data)
+        assert np.array_equal(enc, openssl_ref.ecb(bits, key, data))
+        dec = oracle.mode(oracle.OP_ECB_DEC, key[: bits // 8], bits, None, enc)
+        assert np.array_equal(dec, data)
+        # each block on its own: moving a block moves its ciphertext
+        if nblk >= 3:
+            sw = data.reshape(-1, 16)[[2, 0, 1] + list(range(3, nblk))].reshape(-1)
+            enc2 = oracle.mode(oracle.OP_ECB_ENC, key[: bits // 8], bits, None, sw)
+            assert np.array_equal(enc2.reshape(-1, 16)[:3], enc.reshape(-1, 16)[[2, 0, 1]])
+    with pytest.raises(oracle.OracleError):
+        oracle.mode(oracle.OP_ECB_ENC, np.zeros(16, np.uint8), 128, None, np.zeros(20, np.uint8))
 
 
 @pytest.mark.parametrize("bits", KEY_BITS)
@@ -203,6 +226,8 @@ def _batch_expect_alone(wl, inp):
 
 def test_batch_matches_requests_alone_and_keeps_sentinels():
     wl = workloads.config3(n_reqs=40, max_pages=4)
+    wl.reqs["op"][::7] = oracle.OP_ECB_ENC
+    wl.reqs["op"][3::7] = oracle.OP_ECB_DEC
     # open gaps between requests so that untouched bytes exist
     wl.reqs["offset"] = wl.reqs["offset"] + np.arange(wl.reqs.size, dtype=np.uint64) * 48
     wl.reqs["length"][::3] -= 16
@@ -231,6 +256,15 @@ def test_batch_validation_errors():
         oracle.batch(inp, out, bad, wl.keys, wl.key_bits)
     bad = wl.reqs.copy()
     bad["key_idx"][0] = 7
+    with pytest.raises(oracle.OracleError):
+        oracle.batch(inp, out, bad, wl.keys, wl.key_bits)
+    bad = wl.reqs.copy()
+    bad["op"][2] = 5
+    with pytest.raises(oracle.OracleError):
+        oracle.batch(inp, out, bad, wl.keys, wl.key_bits)
+    bad = wl.reqs.copy()
+    bad["op"][2] = oracle.OP_ECB_DEC
+    bad["length"][2] = 4008
     with pytest.raises(oracle.OracleError):
         oracle.batch(inp, out, bad, wl.keys, wl.key_bits)
     assert not out.any(), "nothing is written on a validation error"
