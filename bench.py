@@ -128,7 +128,7 @@ def bench_batched(dev, iters=3):
     launch per request and a HIP graph of those launches (on the requests of
     the parallel modes; the serial CBC-encrypt chains make per-request
     launches of the whole mix take tens of seconds), plus the chain floor
-    (the longest CBC-encrypt chain alone)."""
+    (the CBC-encrypt chain with the most block rounds, alone)."""
     import numpy as np
     import torch
 
@@ -151,8 +151,12 @@ def bench_batched(dev, iters=3):
     g_plan = aesgpu.Graph.of_plan(plan, d_s, d_in, d_out)
     full_graph_ms = time_gpu(lambda: g_plan.launch(stream), iters, stream)
 
+    # The chain floor: the CBC-encrypt request with the most rounds in all
+    # (blocks x Nr, so an AES-256 chain outweighs an AES-128 one of equal length).
     enc = np.nonzero(wl.reqs["op"] == workloads.OP_CBC_ENC)[0]
-    longest = wl.reqs[enc[np.argmax(wl.reqs["length"][enc])]: enc[np.argmax(wl.reqs["length"][enc])] + 1]
+    nr = wl.key_bits[wl.reqs["key_idx"][enc]] // 32 + 6
+    pick = enc[np.argmax(wl.reqs["length"][enc].astype(np.int64) * nr)]
+    longest = wl.reqs[pick:pick + 1]
     p_long = aesgpu.Plan(ctx, longest, wl.keys.shape[0], nbytes)
     chain_ms = time_gpu(lambda: p_long.launch(d_s, d_in, d_out, stream=stream), iters, stream)
 
@@ -178,6 +182,7 @@ def bench_batched(dev, iters=3):
         "plan_graph_ms": round(full_graph_ms, 3),
         "chain_floor_ms": round(chain_ms, 3),
         "chain_floor_request_bytes": int(longest["length"][0]),
+        "chain_floor_key_bits": int(wl.key_bits[longest["key_idx"][0]]),
         "parallel_subset": {
             "requests": int(par.size), "payload_bytes": par_bytes,
             "one_launch_gbs": gbs(par_bytes, par_batched_ms),
@@ -409,14 +414,23 @@ def main():
 
     payload_step = sum(r[4] for r in runs)
     value = payload_step * args.steps / elapsed / 1e9
+    # A plain device-to-device copy of the same buffer: the HBM bandwidth this
+    # box reaches in practice, to set the runs' traffic against.
+    copy_ms = time_gpu(lambda: d_out.copy_(d_in), 5, stream)
+    copy_gbs = 2 * nbytes / copy_ms / 1e6
+
     per_run = {}
     per_kernel = {}
     for i, (name, kname, _, _, payload, units, _) in enumerate(runs):
         ms = [ev[k][i][0].elapsed_time(ev[k][i][1]) for k in range(args.steps)]
         avg = sum(ms) / len(ms)
+        med = sorted(ms)[len(ms) // 2]
         algo = 2 * payload + units * UNIT_BYTES + 16 * SCHED_BYTES
-        per_run[name] = {"ms": round(avg, 4), "gbs_payload": round(payload / avg / 1e6, 1),
-                         "hbm_frac": round(algo / avg / 1e6 / HBM_PEAK_GBS, 4)}
+        per_run[name] = {"ms": round(avg, 4), "ms_median": round(med, 4),
+                         "ms_min": round(min(ms), 4),
+                         "gbs_payload": round(payload / avg / 1e6, 1),
+                         "hbm_frac": round(algo / avg / 1e6 / HBM_PEAK_GBS, 4),
+                         "frac_of_copy": round(algo / avg / 1e6 / copy_gbs, 4)}
         pk = per_kernel.setdefault(kname, {"ms_total": 0.0, "launches": 0, "algo_bytes": 0})
         pk["ms_total"] += sum(ms)
         pk["launches"] += len(ms)
@@ -492,6 +506,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "per_run": per_run,
+        "hbm_copy_gbs": round(copy_gbs, 1),
         "per_call": per_call,
         "ctr_variants": variants,
         "batched": batched,
