@@ -99,20 +99,24 @@ void aes_ctx_destroy(aes_ctx_t *ctx);
 
 /* ----------------------------------------------------------------- requests */
 
-enum { AES_OP_CBC_ENC = 0, AES_OP_CBC_DEC = 1, AES_OP_CTR = 2 };
+enum { AES_OP_CBC_ENC = 0, AES_OP_CBC_DEC = 1, AES_OP_CTR = 2, AES_OP_ECB_ENC = 3,
+       AES_OP_ECB_DEC = 4 };
 
 /* One service request (paper section 3.2: input buffer, output buffer and a
  * request naming the service).  Bytes [offset, offset+length) of the input
  * buffer are transformed into the same range of the output buffer.
  *   offset: multiple of 16.
- *   length: bytes, < 2^32; a multiple of 16 for CBC; any value for CTR (a
- *           final partial block uses the leading keystream bytes); 0 = no-op.
+ *   length: bytes, < 2^32; a multiple of 16 for CBC and ECB; any value for
+ *           CTR (a final partial block uses the leading keystream bytes);
+ *           0 = no-op.
  *   key_idx: index into the schedule array passed with the call.
- *   op:     AES_OP_CBC_ENC, AES_OP_CBC_DEC or AES_OP_CTR (CTR encrypts and
- *           decrypts alike).
+ *   op:     AES_OP_CBC_ENC, AES_OP_CBC_DEC, AES_OP_CTR (CTR encrypts and
+ *           decrypts alike), AES_OP_ECB_ENC or AES_OP_ECB_DEC (SP 800-38A 6.1:
+ *           every block on its own -- the paper's service mode, section 3.3).
  *   iv:     CBC: the IV.  CTR: the initial counter block T1; bytes 0..7 are a
  *           nonce and bytes 8..15 a big-endian 64-bit counter that advances by
- *           one per block modulo 2^64 without carrying into the nonce.
+ *           one per block modulo 2^64 without carrying into the nonce.  ECB:
+ *           unused.
  * Requests of one call must write pairwise disjoint byte ranges; the input
  * and output buffers are either the same buffer or do not overlap at all. */
 typedef struct aes_req {
@@ -139,7 +143,8 @@ int aes_batch(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
 /* Single-mode forms of aes_batch with the requests given as parallel host
  * arrays: offsets[i], lengths[i], key_idx[i] and ivs[16*i .. 16*i+15] form
  * request i; every request uses the mode the name says (SP 800-38A 6.2 CBC
- * encryption / decryption, 6.5 CTR).  Same errors as aes_batch. */
+ * encryption / decryption, 6.5 CTR, 6.1 ECB; the ECB forms take no IVs and
+ * ignore ivs, which may be NULL).  Same errors as aes_batch. */
 int aes_cbc_encrypt_batch(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
                           const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
                           const uint64_t *offsets, const uint64_t *lengths,
@@ -154,6 +159,16 @@ int aes_ctr_batch(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_sch
                   const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
                   const uint64_t *offsets, const uint64_t *lengths,
                   const uint32_t *key_idx, const uint8_t *ivs, uint64_t n, void *stream);
+int aes_ecb_encrypt_batch(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+                          const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
+                          const uint64_t *offsets, const uint64_t *lengths,
+                          const uint32_t *key_idx, const uint8_t *ivs, uint64_t n,
+                          void *stream);
+int aes_ecb_decrypt_batch(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+                          const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
+                          const uint64_t *offsets, const uint64_t *lengths,
+                          const uint32_t *key_idx, const uint8_t *ivs, uint64_t n,
+                          void *stream);
 
 /* -------------------------------------------------------------------- plans */
 
@@ -166,15 +181,17 @@ typedef struct aes_plan aes_plan_t;
 
 /* One work unit of a plan, 32 bytes (the device record the kernels read):
  *   offset, nbytes: the byte range the unit covers.
- *   meta: bits 0..23 schedule index, bits 24..25 op, bit 26 set when a CBC
+ *   meta: bits 0..23 schedule index, bits 24..26 op, bit 27 set when a CBC
  *         decryption unit takes its predecessor block from the 16 input bytes
  *         before offset (every tile of a request but the first).
  *   w: CTR -- nonce bytes 0..3 and 4..7 as little-endian words, then the
  *      64-bit counter of the unit's first block (w[2] low, w[3] high half);
- *      CBC -- the IV as four little-endian words (first unit of a request).
- * CTR and CBC-decryption requests become tiles of the context's tile size
- * (4096 bytes by default); each CBC-encryption request is one unit (a serial
- * chain), and chains are grouped by key, longest first within a key. */
+ *      CBC -- the IV as four little-endian words (first unit of a request);
+ *      ECB -- zero.
+ * CTR, ECB and CBC-decryption requests become tiles of the context's tile
+ * size (4096 bytes by default); each CBC-encryption request is one unit (a
+ * serial chain), and chains are grouped by key, longest first within a
+ * key. */
 typedef struct aes_unit {
     uint64_t offset;
     uint32_t nbytes;
@@ -183,8 +200,8 @@ typedef struct aes_unit {
 } aes_unit_t;
 
 typedef struct aes_plan_info {
-    uint64_t n_units_cbc_dec;
-    uint64_t n_units_ctr;
+    uint64_t n_units_cbc_dec;  /* decryption-table tiles: CBC and ECB decryption */
+    uint64_t n_units_ctr;      /* encryption-table tiles: CTR, then ECB encryption */
     uint64_t n_chains_cbc_enc;
     uint64_t payload_bytes; /* sum of request lengths */
     uint64_t extent_bytes;  /* max(offset + length) */
@@ -204,9 +221,10 @@ int aes_plan_create(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint
 int aes_plan_launch(aes_plan_t *plan, const aes_schedule_t *d_scheds, const uint8_t *d_in,
                     uint8_t *d_out, void *stream);
 int aes_plan_info(const aes_plan_t *plan, aes_plan_info_t *info);
-/* Copies up to max unit records (CBC-decrypt tiles, then CTR tiles grouped by
- * key, then chains grouped by key, longest first within a key) to out and
- * sets *n_out to the plan's total unit count. */
+/* Copies up to max unit records (CBC- and ECB-decrypt tiles, then CTR tiles
+ * grouped by key, then ECB-encrypt tiles grouped by key, then chains grouped
+ * by key, longest first within a key) to out and sets *n_out to the plan's
+ * total unit count. */
 int aes_plan_units(const aes_plan_t *plan, aes_unit_t *out, uint64_t max, uint64_t *n_out);
 /* Waits for the device to be idle, then frees the plan.  NULL is a no-op. */
 void aes_plan_destroy(aes_plan_t *plan);
@@ -362,8 +380,9 @@ int aes_server_create(aes_ctx_t *ctx, const aes_server_config_t *cfg, aes_server
  * stopped first and relaunched by the next submit. */
 int aes_server_set_key(aes_server_t *srv, uint32_t slot, const aes_schedule_t *host_sched);
 /* Posts one request (paper section 3.2: buffers, a service request, an
- * optional completion callback).  op and iv as in aes_req_t; length > 0,
- * < 2^32, a multiple of 16 for CBC.  Sets *ticket.  Errors: AES_ERR_ARG,
+ * optional completion callback).  op and iv as in aes_req_t (iv may be NULL
+ * for ECB); length > 0, < 2^32, a multiple of 16 for CBC and ECB.  Sets
+ * *ticket.  Errors: AES_ERR_ARG,
  * AES_ERR_LENGTH, AES_ERR_RANGE (key slot), AES_ERR_OVERLAP, AES_ERR_AGAIN
  * (admission), AES_ERR_DEVICE. */
 int aes_server_submit(aes_server_t *srv, uint32_t op, uint32_t key_slot, const uint8_t iv[16],

@@ -37,6 +37,8 @@ AES_ERR_STATE = -10
 AES_OP_CBC_ENC = 0
 AES_OP_CBC_DEC = 1
 AES_OP_CTR = 2
+AES_OP_ECB_ENC = 3
+AES_OP_ECB_DEC = 4
 AES_DEVICE_NONE = -1
 AES_CTR_TABLE = 0
 AES_CTR_BITSLICE = 1
@@ -92,6 +94,8 @@ def lib():
             "aes_cbc_encrypt_batch": (i32, [p, p, u32, p, p, u64, p, p, p, p, u64, p]),
             "aes_cbc_decrypt_batch": (i32, [p, p, u32, p, p, u64, p, p, p, p, u64, p]),
             "aes_ctr_batch": (i32, [p, p, u32, p, p, u64, p, p, p, p, u64, p]),
+            "aes_ecb_encrypt_batch": (i32, [p, p, u32, p, p, u64, p, p, p, p, u64, p]),
+            "aes_ecb_decrypt_batch": (i32, [p, p, u32, p, p, u64, p, p, p, p, u64, p]),
             "aes_plan_create": (i32, [p, p, u64, u32, u64, ctypes.POINTER(p)]),
             "aes_plan_launch": (i32, [p, p, p, p, p]),
             "aes_plan_info": (i32, [p, p]),
@@ -242,14 +246,15 @@ def _single(name, ctx, d_scheds, d_in, d_out, offsets, lengths, key_idx, ivs, bu
     off = np.ascontiguousarray(offsets, dtype=np.uint64)
     ln = np.ascontiguousarray(lengths, dtype=np.uint64)
     ki = np.ascontiguousarray(key_idx, dtype=np.uint32)
-    iv = np.ascontiguousarray(ivs, dtype=np.uint8).reshape(-1)
     n = off.size
-    if ln.size != n or ki.size != n or iv.size != 16 * n:
+    iv = None if ivs is None else np.ascontiguousarray(ivs, dtype=np.uint8).reshape(-1)
+    if ln.size != n or ki.size != n or (iv is not None and iv.size != 16 * n):
         raise ValueError("offsets, lengths, key_idx and ivs must describe the same requests")
     bb = _nbytes(d_in) if buf_bytes is None else buf_bytes
     _check(getattr(lib(), name)(ctx.handle, _ptr(d_scheds), _sched_count(d_scheds, n_scheds),
                                 _ptr(d_in), _ptr(d_out), bb, off.ctypes.data, ln.ctypes.data,
-                                ki.ctypes.data, iv.ctypes.data, n, _stream(stream)), name)
+                                ki.ctypes.data, None if iv is None else iv.ctypes.data, n,
+                                _stream(stream)), name)
 
 
 def cbc_encrypt_batch(ctx, d_scheds, d_in, d_out, offsets, lengths, key_idx, ivs,
@@ -267,6 +272,20 @@ def cbc_decrypt_batch(ctx, d_scheds, d_in, d_out, offsets, lengths, key_idx, ivs
 def ctr_batch(ctx, d_scheds, d_in, d_out, offsets, lengths, key_idx, ivs,
               buf_bytes=None, n_scheds=None, stream=None):
     _single("aes_ctr_batch", ctx, d_scheds, d_in, d_out, offsets, lengths, key_idx, ivs,
+            buf_bytes, n_scheds, stream)
+
+
+def ecb_encrypt_batch(ctx, d_scheds, d_in, d_out, offsets, lengths, key_idx, ivs=None,
+                      buf_bytes=None, n_scheds=None, stream=None):
+    """aes_ecb_encrypt_batch (ECB takes no IVs; ivs is ignored and may be None)."""
+    _single("aes_ecb_encrypt_batch", ctx, d_scheds, d_in, d_out, offsets, lengths, key_idx, ivs,
+            buf_bytes, n_scheds, stream)
+
+
+def ecb_decrypt_batch(ctx, d_scheds, d_in, d_out, offsets, lengths, key_idx, ivs=None,
+                      buf_bytes=None, n_scheds=None, stream=None):
+    """aes_ecb_decrypt_batch (ECB takes no IVs; ivs is ignored and may be None)."""
+    _single("aes_ecb_decrypt_batch", ctx, d_scheds, d_in, d_out, offsets, lengths, key_idx, ivs,
             buf_bytes, n_scheds, stream)
 
 
@@ -461,8 +480,9 @@ class Server:
         """Posts a request; returns its ticket.  Raises AesError (status
         AES_ERR_AGAIN when admission refuses).  callback(done_record) runs on
         the library's completion thread."""
-        ivb = np.ascontiguousarray(np.frombuffer(bytes(iv), np.uint8)
-                                   if not isinstance(iv, np.ndarray) else iv, dtype=np.uint8)
+        ivb = None if iv is None else np.ascontiguousarray(
+            np.frombuffer(bytes(iv), np.uint8) if not isinstance(iv, np.ndarray) else iv,
+            dtype=np.uint8)
         t = ctypes.c_uint64()
         cb = None
         if callback is not None:
@@ -471,7 +491,8 @@ class Server:
                                     DONE_DTYPE)[0]
                 _f(rec)
             cb = DONE_CB(_tramp)
-        st = lib().aes_server_submit(self.handle, op, key_slot, ivb.ctypes.data, _ptr(d_src),
+        st = lib().aes_server_submit(self.handle, op, key_slot,
+                                     None if ivb is None else ivb.ctypes.data, _ptr(d_src),
                                      _ptr(d_dst), length,
                                      ctypes.cast(cb, ctypes.c_void_p) if cb else None, None,
                                      ctypes.byref(t))

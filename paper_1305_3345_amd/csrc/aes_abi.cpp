@@ -54,7 +54,7 @@ int validate(const aes_req_t *reqs, uint64_t n, uint32_t n_scheds, uint64_t buf_
     uint64_t last_off = 0;
     for (uint64_t i = 0; i < n; i++) {
         const aes_req_t &r = reqs[i];
-        if (r.op > AES_OP_CTR)
+        if (r.op > AES_OP_ECB_DEC)
             return AES_ERR_ARG;
         if (r.length > MAX_REQ_BYTES)
             return AES_ERR_LENGTH;
@@ -129,25 +129,29 @@ inline uint64_t be64(const uint8_t *p) {
 }
 
 struct Planned {
-    std::vector<Unit> dec;     // CBC-decrypt tiles
-    std::vector<Unit> ctr;     // CTR tiles
+    std::vector<Unit> dec;     // CBC- and ECB-decrypt tiles
+    std::vector<Unit> ctr;     // CTR tiles, then ECB-encrypt tiles (the last n_ecb)
     std::vector<Unit> chains;  // CBC-encrypt chains, by key, longest first within a key
     uint64_t payload = 0;
     uint64_t extent = 0;
     uint64_t dec_bytes = 0, ctr_bytes = 0, chain_bytes = 0;
     bool dec_has_pred_in = false;
+    size_t n_ecb = 0;  // ECB-encrypt tiles at the end of ctr
 };
 
-// Cuts every request into units: CTR and CBC-decrypt into tile_bytes tiles
-// (a multiple of 16), CBC-encrypt into one chain each.
+bool is_dec_tile_op(uint32_t op) { return op == AES_OP_CBC_DEC || op == AES_OP_ECB_DEC; }
+bool is_enc_tile_op(uint32_t op) { return op == AES_OP_CTR || op == AES_OP_ECB_ENC; }
+
+// Cuts every request into units: CTR, ECB and CBC-decrypt into tile_bytes
+// tiles (a multiple of 16), CBC-encrypt into one chain each.
 int plan_units(const aes_req_t *reqs, uint64_t n, uint32_t tile_bytes, Planned &p) {
     try {
         uint64_t n_tiles_ctr = 0, n_tiles_dec = 0, n_chain = 0;
         for (uint64_t i = 0; i < n; i++) {
             const uint64_t t = (reqs[i].length + tile_bytes - 1) / tile_bytes;
-            if (reqs[i].op == AES_OP_CTR)
+            if (is_enc_tile_op(reqs[i].op))
                 n_tiles_ctr += t;
-            else if (reqs[i].op == AES_OP_CBC_DEC)
+            else if (is_dec_tile_op(reqs[i].op))
                 n_tiles_dec += t;
             else if (reqs[i].length)
                 n_chain++;
@@ -164,7 +168,7 @@ int plan_units(const aes_req_t *reqs, uint64_t n, uint32_t tile_bytes, Planned &
             p.payload += r.length;
             p.extent = std::max(p.extent, r.offset + r.length);
             (r.op == AES_OP_CBC_ENC ? p.chain_bytes
-                                    : r.op == AES_OP_CTR ? p.ctr_bytes : p.dec_bytes) += r.length;
+                                    : is_enc_tile_op(r.op) ? p.ctr_bytes : p.dec_bytes) += r.length;
             const uint32_t meta_base = r.key_idx | (r.op << META_OP_SHIFT);
             if (r.op == AES_OP_CBC_ENC) {
                 Unit u;
@@ -189,6 +193,11 @@ int plan_units(const aes_req_t *reqs, uint64_t n, uint32_t tile_bytes, Planned &
                     u.w[2] = (uint32_t)c;
                     u.w[3] = (uint32_t)(c >> 32);
                     p.ctr.push_back(u);
+                } else if (r.op == AES_OP_ECB_ENC || r.op == AES_OP_ECB_DEC) {
+                    u.w[0] = u.w[1] = u.w[2] = u.w[3] = 0;  // every block on its own
+                    (r.op == AES_OP_ECB_ENC ? p.ctr : p.dec).push_back(u);
+                    if (r.op == AES_OP_ECB_ENC)
+                        p.n_ecb++;
                 } else {
                     if (pos == 0) {
                         for (int w = 0; w < 4; w++)
@@ -204,7 +213,12 @@ int plan_units(const aes_req_t *reqs, uint64_t n, uint32_t tile_bytes, Planned &
         }
         // CTR tiles grouped by key (request order kept within a key): the
         // bitsliced kernel shares one key schedule across a wave's 8 tiles.
+        // ECB-encrypt tiles follow them (the bitsliced kernel does CTR only).
         std::stable_sort(p.ctr.begin(), p.ctr.end(), [](const Unit &a, const Unit &b) {
+            const bool ea = unit_op(a.meta) == AES_OP_ECB_ENC;
+            const bool eb = unit_op(b.meta) == AES_OP_ECB_ENC;
+            if (ea != eb)
+                return eb;
             return (a.meta & META_KEY_MASK) < (b.meta & META_KEY_MASK);
         });
         // Chains grouped by key, longest first within a key: a wave runs the
@@ -289,11 +303,12 @@ struct PlanView {
     size_t n_dec, n_ctr, n_chain;
     bool pred_in;
     uint64_t dec_bytes, ctr_bytes;
+    size_t n_ecb;  // ECB-encrypt tiles: the last n_ecb of the n_ctr encryption tiles
 };
 
 PlanView view_of(const Planned &p, void *d_units) {
     return PlanView{d_units, p.dec.size(), p.ctr.size(), p.chains.size(), p.dec_has_pred_in,
-                    p.dec_bytes, p.ctr_bytes};
+                    p.dec_bytes, p.ctr_bytes, p.n_ecb};
 }
 
 // Workgroups of the fused kernel that hold the decryption tables: a share of
@@ -326,13 +341,16 @@ int launch_planned(aes_ctx *ctx, const PlanView &v, const aes_schedule_t *d_sche
         if ((e = launch_snapshot_preds(u_dec, (uint32_t)v.n_dec, d_in, d_preds, stream)))
             return hip_fail((hipError_t)e);
     }
-    // The bitsliced CTR kernel has a launch of its own; the fused kernel then
-    // takes only the CBC units.
-    const bool bitslice = ctx->ctr_variant == AES_CTR_BITSLICE && v.n_ctr;
-    if (bitslice && (e = launch_ctr_bitslice(u_ctr, (uint32_t)v.n_ctr, d_scheds, n_scheds, d_in,
-                                             d_out, ctx->n_cu, stream)))
+    // The bitsliced CTR kernel has a launch of its own for the CTR tiles; the
+    // table kernels then take only the ECB-encrypt tiles of that range.
+    const size_t n_ctr_only = v.n_ctr - v.n_ecb;
+    const bool bitslice = ctx->ctr_variant == AES_CTR_BITSLICE && n_ctr_only;
+    if (bitslice && (e = launch_ctr_bitslice(u_ctr, (uint32_t)n_ctr_only, d_scheds, n_scheds,
+                                             d_in, d_out, ctx->n_cu, stream)))
         return hip_fail((hipError_t)e);
-    const size_t n_ctr_tab = bitslice ? 0 : v.n_ctr;
+    if (bitslice)
+        u_ctr += n_ctr_only;
+    const size_t n_ctr_tab = bitslice ? v.n_ecb : v.n_ctr;
     const int kinds = (v.n_dec > 0) + (n_ctr_tab > 0) + (v.n_chain > 0);
     if (ctx->fuse && kinds > 1) {
         const int grid = ctx->grid > 0 ? ctx->grid : ctx->n_cu;
@@ -351,7 +369,8 @@ int launch_planned(aes_ctx *ctx, const PlanView &v, const aes_schedule_t *d_sche
         a.n_sched = n_scheds;
         PlanView fused = v;
         fused.n_ctr = n_ctr_tab;
-        fused.ctr_bytes = bitslice ? 0 : v.ctr_bytes;
+        fused.ctr_bytes = bitslice ? (v.n_ctr ? v.ctr_bytes * v.n_ecb / v.n_ctr : 0)
+                                   : v.ctr_bytes;
         a.n_dec_wg = dec_workgroups(fused, grid);
         a.chain_lanes = (uint32_t)ctx->chain.lanes;
         a.chain_quad = ctx->chain.quad ? 1u : 0u;
@@ -444,7 +463,8 @@ int single_mode(uint32_t op, aes_ctx *ctx, const aes_schedule_t *d_scheds, uint3
                 void *stream) {
     if (!ctx)
         return AES_ERR_ARG;
-    if (n && (!offsets || !lengths || !key_idx || !ivs))
+    const bool ecb = op == AES_OP_ECB_ENC || op == AES_OP_ECB_DEC;  // no IVs
+    if (n && (!offsets || !lengths || !key_idx || (!ivs && !ecb)))
         return AES_ERR_ARG;
     std::vector<aes_req_t> reqs;
     try {
@@ -457,7 +477,10 @@ int single_mode(uint32_t op, aes_ctx *ctx, const aes_schedule_t *d_scheds, uint3
         reqs[i].length = lengths[i];
         reqs[i].key_idx = key_idx[i];
         reqs[i].op = op;
-        memcpy(reqs[i].iv, ivs + 16 * i, 16);
+        if (ecb)
+            memset(reqs[i].iv, 0, 16);
+        else
+            memcpy(reqs[i].iv, ivs + 16 * i, 16);
     }
     return run_batch(ctx, d_scheds, n_scheds, d_in, d_out, buf_bytes, reqs.data(), n, stream);
 }
@@ -588,6 +611,24 @@ int aes_ctr_batch(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_sch
                   const uint64_t *offsets, const uint64_t *lengths, const uint32_t *key_idx,
                   const uint8_t *ivs, uint64_t n, void *stream) {
     return single_mode(AES_OP_CTR, ctx, d_scheds, n_scheds, d_in, d_out, buf_bytes, offsets,
+                       lengths, key_idx, ivs, n, stream);
+}
+
+int aes_ecb_encrypt_batch(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+                          const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
+                          const uint64_t *offsets, const uint64_t *lengths,
+                          const uint32_t *key_idx, const uint8_t *ivs, uint64_t n,
+                          void *stream) {
+    return single_mode(AES_OP_ECB_ENC, ctx, d_scheds, n_scheds, d_in, d_out, buf_bytes, offsets,
+                       lengths, key_idx, ivs, n, stream);
+}
+
+int aes_ecb_decrypt_batch(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+                          const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
+                          const uint64_t *offsets, const uint64_t *lengths,
+                          const uint32_t *key_idx, const uint8_t *ivs, uint64_t n,
+                          void *stream) {
+    return single_mode(AES_OP_ECB_DEC, ctx, d_scheds, n_scheds, d_in, d_out, buf_bytes, offsets,
                        lengths, key_idx, ivs, n, stream);
 }
 

@@ -78,7 +78,9 @@ __global__ __launch_bounds__(256, 2) void k_ctr_bitslice(const Unit *__restrict_
             const Unit un = units[u];
             off = un.off;
             nbytes = un.nbytes;
-            key = un.meta & META_KEY_MASK;
+            // CTR units only (the planner places them first): anything else
+            // gets an out-of-range key and is skipped
+            key = unit_op(un.meta) == AES_OP_CTR ? un.meta & META_KEY_MASK : 0xFFFFFFFFu;
             w0 = un.w[0];
             w1 = un.w[1];
             w2 = un.w[2];

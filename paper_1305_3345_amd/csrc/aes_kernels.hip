@@ -145,6 +145,8 @@ __device__ __forceinline__ Unit request_unit(const aes_req_t &r, uint32_t t, uin
         u.w[1] = w[1];
         u.w[2] = (uint32_t)c;
         u.w[3] = (uint32_t)(c >> 32);
+    } else if (r.op == AES_OP_ECB_ENC || r.op == AES_OP_ECB_DEC) {
+        u.w[0] = u.w[1] = u.w[2] = u.w[3] = 0u;
     } else if (t == 0 || r.op == AES_OP_CBC_ENC) {
         u.w[0] = w[0];
         u.w[1] = w[1];
@@ -327,7 +329,7 @@ int launch_request(const aes_req_t &r, uint32_t tile, const aes_schedule_t *d_sc
         grid = 1;
         waves = 1;
     }
-    if (r.op == AES_OP_CBC_DEC)
+    if (r.op == AES_OP_CBC_DEC || r.op == AES_OP_ECB_DEC)
         hipLaunchKernelGGL((k_request<true, 2>), dim3(grid), dim3(64 * waves), 0,
                            (hipStream_t)stream, r, tile, d_sched, n_sched, d_timg, d_in, d_out);
     else

@@ -247,7 +247,42 @@ __device__ __forceinline__ void ctr_unit(const uint32_t *lds, uint32_t L0,
     }
 }
 
-// Key checks and round-count dispatch for one CTR unit (wave-uniform).
+// SP 800-38A 6.1: ECB encryption, every block on its own (whole blocks).
+template <int NB, int NR>
+__device__ __forceinline__ void ecb_enc_unit(const uint32_t *lds, uint32_t L0, uint32_t lane,
+                                             const Unit &un, const uint32_t *__restrict__ rk,
+                                             const uint8_t *in, uint8_t *out) {
+    const uint32_t nbytes = un.nbytes;
+    const uint32_t nblk = nbytes >> 4;
+    const uint8_t *src = in + un.off;
+    uint8_t *dst = out + un.off;
+    const uint32_t zero[4] = {0u, 0u, 0u, 0u};
+    for (uint32_t base = 0; base < nblk; base += 64u * NB) {
+        uint32_t s[NB][4];
+#pragma unroll
+        for (int i = 0; i < NB; i++) {
+            load_block(src, base + 64u * i + lane, nbytes, s[i]);
+#pragma unroll
+            for (int w = 0; w < 4; w++)
+                s[i][w] ^= rk[w];
+        }
+#pragma unroll
+        for (int r = 1; r < NR; r++) {
+#pragma unroll
+            for (int i = 0; i < NB; i++)
+                enc_round(lds, s[i], rk + 4 * r, L0);
+        }
+#pragma unroll
+        for (int i = 0; i < NB; i++) {
+            uint32_t o[4];
+            enc_last(lds, s[i], rk + 4 * NR, L0, zero, o);
+            store_block(dst, base + 64u * i + lane, nbytes, o);
+        }
+    }
+}
+
+// Key checks and round-count dispatch for one encryption-table tile (CTR
+// or ECB encryption; wave-uniform).
 template <int NB>
 __device__ __forceinline__ void run_ctr_unit(const uint32_t *lds, uint32_t L0,
                                              uint32_t lane, const Unit &un,
@@ -258,6 +293,15 @@ __device__ __forceinline__ void run_ctr_unit(const uint32_t *lds, uint32_t L0,
         return;
     const aes_schedule_t *ks = sched + key;
     const uint32_t nr = ks->nr;
+    if (unit_op(un.meta) == AES_OP_ECB_ENC) {
+        if (nr == 10)
+            ecb_enc_unit<NB, 10>(lds, L0, lane, un, ks->ek, in, out);
+        else if (nr == 12)
+            ecb_enc_unit<NB, 12>(lds, L0, lane, un, ks->ek, in, out);
+        else if (nr == 14)
+            ecb_enc_unit<NB, 14>(lds, L0, lane, un, ks->ek, in, out);
+        return;
+    }
     if (nr == 10)
         ctr_unit<NB, 10>(lds, L0, lane, un, ks->ek, in, out);
     else if (nr == 12)
@@ -275,8 +319,9 @@ __device__ __forceinline__ uint32_t shift_up(uint32_t old, uint32_t v) {
 
 // SP 800-38A 6.2: P_j = D(C_j) ^ C_(j-1).  Lane l of step i decrypts block
 // 64i + l; its predecessor is lane l-1's ciphertext, and lane 0 takes lane 63
-// of the previous step (or the block before the unit).
-template <int NB, int NR>
+// of the previous step (or the block before the unit).  ECB (6.1): P_j =
+// D(C_j), no chaining.
+template <int NB, int NR, bool ECB = false>
 __device__ __forceinline__ void cbcdec_unit(const uint32_t *lds, uint32_t L0,
                                             uint32_t L2, uint32_t lane, const Unit &un,
                                             const uint4 *snap, const uint32_t *__restrict__ dk,
@@ -286,7 +331,9 @@ __device__ __forceinline__ void cbcdec_unit(const uint32_t *lds, uint32_t L0,
     const uint8_t *src = in + un.off;
     uint8_t *dst = out + un.off;
     uint32_t carry[4];
-    if (un.meta & FLAG_PRED_IN) {
+    if (ECB) {
+        carry[0] = carry[1] = carry[2] = carry[3] = 0u;
+    } else if (un.meta & FLAG_PRED_IN) {
         const uint4 p = snap ? *snap : *reinterpret_cast<const uint4 *>(src - 16);
         carry[0] = p.x;
         carry[1] = p.y;
@@ -307,15 +354,22 @@ __device__ __forceinline__ void cbcdec_unit(const uint32_t *lds, uint32_t L0,
         for (int i = 0; i < NB; i++) {
 #pragma unroll
             for (int w = 0; w < 4; w++) {
-                const uint32_t prev_last =
-                    i == 0 ? carry[w] : (uint32_t)__builtin_amdgcn_readlane((int)c[i - 1][w], 63);
-                pred[i][w] = shift_up(prev_last, c[i][w]);
+                if (ECB) {
+                    pred[i][w] = 0u;
+                } else {
+                    const uint32_t prev_last =
+                        i == 0 ? carry[w]
+                               : (uint32_t)__builtin_amdgcn_readlane((int)c[i - 1][w], 63);
+                    pred[i][w] = shift_up(prev_last, c[i][w]);
+                }
                 s[i][w] = c[i][w] ^ dk[w];
             }
         }
+        if (!ECB) {
 #pragma unroll
-        for (int w = 0; w < 4; w++)
-            carry[w] = (uint32_t)__builtin_amdgcn_readlane((int)c[NB - 1][w], 63);
+            for (int w = 0; w < 4; w++)
+                carry[w] = (uint32_t)__builtin_amdgcn_readlane((int)c[NB - 1][w], 63);
+        }
 #pragma unroll
         for (int r = 1; r < NR; r++) {
 #pragma unroll
@@ -342,6 +396,15 @@ __device__ __forceinline__ void run_dec_unit(const uint32_t *lds, uint32_t L0,
         return;
     const aes_schedule_t *ks = sched + key;
     const uint32_t nr = ks->nr;
+    if (unit_op(un.meta) == AES_OP_ECB_DEC) {
+        if (nr == 10)
+            cbcdec_unit<NB, 10, true>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
+        else if (nr == 12)
+            cbcdec_unit<NB, 12, true>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
+        else if (nr == 14)
+            cbcdec_unit<NB, 14, true>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
+        return;
+    }
     if (nr == 10)
         cbcdec_unit<NB, 10>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
     else if (nr == 12)

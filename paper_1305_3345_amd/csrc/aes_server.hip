@@ -185,7 +185,7 @@ __device__ void dispatch_loop(const ServeArgs &a) {
                 __hip_atomic_store(&a.done[slot].units, k_units, __ATOMIC_RELAXED, SYS);
             // The host validates every request; these checks keep a bad
             // descriptor from reaching the kernels.
-            const bool ok = op <= AES_OP_CTR && key < a.n_keys && r_len > 0 &&
+            const bool ok = op <= AES_OP_ECB_DEC && key < a.n_keys && r_len > 0 &&
                             r_len <= a.max_bytes && (op == AES_OP_CTR || (r_len & 15u) == 0) &&
                             r_src && r_dst;
             if (!ok) {
@@ -193,7 +193,7 @@ __device__ void dispatch_loop(const ServeArgs &a) {
                     complete(a, slot, ticket, AES_ERR_ARG);
                 continue;
             }
-            const int qi = op == AES_OP_CBC_DEC ? 1 : 0;
+            const int qi = op == AES_OP_CBC_DEC || op == AES_OP_ECB_DEC ? 1 : 0;
             const uint32_t k = k_units;
             // No wait for room: the host admits at most queue_units units
             // per queue in flight, so published units are never overwritten
@@ -215,6 +215,8 @@ __device__ void dispatch_loop(const ServeArgs &a) {
                     su.u.w[1] = w1;
                     su.u.w[2] = (uint32_t)c;
                     su.u.w[3] = (uint32_t)(c >> 32);
+                } else if (op == AES_OP_ECB_ENC || op == AES_OP_ECB_DEC) {
+                    su.u.w[0] = su.u.w[1] = su.u.w[2] = su.u.w[3] = 0u;
                 } else if (j == 0) {
                     su.u.w[0] = w0;
                     su.u.w[1] = w1;
@@ -323,7 +325,7 @@ __device__ void worker_loop(const ServeArgs &a, const uint32_t *lds) {
         uint8_t *dst = (uint8_t *)__hip_atomic_load(&p->dst, __ATOMIC_RELAXED, AGT);
         const uint64_t ticket = __hip_atomic_load(&p->ticket, __ATOMIC_RELAXED, AGT);
         const uint32_t slot = __hip_atomic_load(&p->slot, __ATOMIC_RELAXED, AGT);
-        const uint32_t op = (un.meta >> META_OP_SHIFT) & 3u;
+        const uint32_t op = unit_op(un.meta);
         if (DEC) {
             run_dec_unit<1>(lds, L0, L2, lane, un, nullptr, a.keys, a.n_keys, src, dst);
         } else if (op == AES_OP_CBC_ENC) {
@@ -591,7 +593,8 @@ void poll_loop(aes_server *s) {
 
 int check_request(aes_server *s, uint32_t op, uint32_t key_slot, const uint8_t *iv,
                   const uint8_t *src, uint8_t *dst, uint64_t length) {
-    if (op > AES_OP_CTR || !iv || !src || !dst || !length)
+    const bool ecb = op == AES_OP_ECB_ENC || op == AES_OP_ECB_DEC;  // no IV
+    if (op > AES_OP_ECB_DEC || (!iv && !ecb) || !src || !dst || !length)
         return AES_ERR_ARG;
     if (length > (1ull << 32) - 16 || (op != AES_OP_CTR && (length & 15)))
         return AES_ERR_LENGTH;
@@ -620,7 +623,7 @@ int submit_locked(aes_server *s, uint32_t op, uint32_t key_slot, const uint8_t *
                            length > s->cfg.max_request_bytes;
     // Units this request adds to its device queue; the queue never holds
     // more than queue_units unconsumed units (see the dispatcher).
-    const int queue = op == AES_OP_CBC_DEC ? 1 : 0;
+    const int queue = op == AES_OP_CBC_DEC || op == AES_OP_ECB_DEC ? 1 : 0;
     const uint32_t units =
         by_launch ? 0u : (op == AES_OP_CBC_ENC ? 1u : (uint32_t)((length + 4095) / 4096));
     if (s->inflight_units[queue] + units > s->cfg.queue_units) {
@@ -633,7 +636,10 @@ int submit_locked(aes_server *s, uint32_t op, uint32_t key_slot, const uint8_t *
         r.length = length;
         r.key_idx = key_slot;
         r.op = op;
-        memcpy(r.iv, iv, 16);
+        if (iv)
+            memcpy(r.iv, iv, 16);
+        else
+            memset(r.iv, 0, 16);
         hipStream_t st = s->cfg.mode == AES_SERVE_PER_LAUNCH
                              ? s->streams[ticket % s->streams.size()]
                              : s->fbstream;
@@ -653,7 +659,10 @@ int submit_locked(aes_server *s, uint32_t op, uint32_t key_slot, const uint8_t *
         d->key_slot = key_slot;
         d->op = op;
         d->reserved = 0;
-        memcpy(d->iv, iv, 16);
+        if (iv)
+            memcpy(d->iv, iv, 16);
+        else
+            memset(d->iv, 0, 16);
         d->t_submit = t_submit;
         __atomic_store_n(&d->seq, ticket + 1, __ATOMIC_RELEASE);
         if (!s->running) {

@@ -13,7 +13,7 @@ namespace aesgpu {
 struct Unit {
     uint64_t off;     // byte offset of the unit's first byte (input and output)
     uint32_t nbytes;  // bytes in the unit
-    uint32_t meta;    // bits 0..23 schedule index, bits 24..25 op, bits 26..31 flags
+    uint32_t meta;    // bits 0..23 schedule index, bits 24..26 op, bits 27..31 flags
     uint32_t w[4];    // CTR: nonce words 0,1 then the 64-bit counter of the unit's
                       //      first block as an integer (w[2] low half, w[3] high half)
                       // CBC: the 16 bytes that precede the unit's first block in
@@ -23,7 +23,12 @@ static_assert(sizeof(Unit) == 32, "Unit is 32 bytes");
 
 constexpr uint32_t META_KEY_MASK = 0x00FFFFFFu;
 constexpr uint32_t META_OP_SHIFT = 24;
-constexpr uint32_t FLAG_PRED_IN = 1u << 26;  // CBC-dec: predecessor is in[off-16 .. off)
+constexpr uint32_t META_OP_MASK = 7u;        // op in bits 24..26
+constexpr uint32_t FLAG_PRED_IN = 1u << 27;  // CBC-dec: predecessor is in[off-16 .. off)
+
+__host__ __device__ inline uint32_t unit_op(uint32_t meta) {
+    return (meta >> META_OP_SHIFT) & META_OP_MASK;
+}
 constexpr uint32_t MAX_KEYS = 1u << 24;
 
 // Table image in device memory (2304 words), written once per context:

@@ -35,7 +35,8 @@ def run_gpu(ctx, wl, inp: np.ndarray, form: str = "batch", inplace: bool = False
         ops = np.unique(reqs["op"])
         assert ops.size == 1
         fn = {a.AES_OP_CBC_ENC: a.cbc_encrypt_batch, a.AES_OP_CBC_DEC: a.cbc_decrypt_batch,
-              a.AES_OP_CTR: a.ctr_batch}[int(ops[0])]
+              a.AES_OP_CTR: a.ctr_batch, a.AES_OP_ECB_ENC: a.ecb_encrypt_batch,
+              a.AES_OP_ECB_DEC: a.ecb_decrypt_batch}[int(ops[0])]
         fn(ctx, d_scheds, d_in, d_out, reqs["offset"], reqs["length"], reqs["key_idx"],
            reqs["iv"])
     elif form == "plan":

@@ -117,7 +117,7 @@ def test_validation_errors(ag, hctx, case, status):
         reqs["length"][0] = 32
         reqs["offset"][2] = 0
     elif case == "bad_op":
-        reqs["op"][1] = 3
+        reqs["op"][1] = 5
     elif case == "huge":
         reqs["length"][0] = 1 << 32
     elif case == "alias":
@@ -165,7 +165,7 @@ def _check_plan(ag, plan, reqs, tile):
     units = plan.units()
     info = plan.info()
     assert info["payload_bytes"] == int(reqs["length"].sum())
-    op_of = (units["meta"] >> 24) & 3
+    op_of = (units["meta"] >> 24) & 7
     covered = {}
     for u in units:
         covered.setdefault(int(u["offset"]), []).append(u)
@@ -180,7 +180,7 @@ def _check_plan(ag, plan, reqs, tile):
             us = covered.get(off + pos)
             assert us and len(us) == 1, (off, pos)
             u = us[0]
-            assert ((int(u["meta"]) >> 24) & 3) == op
+            assert ((int(u["meta"]) >> 24) & 7) == op
             assert (int(u["meta"]) & 0xFFFFFF) == int(r["key_idx"])
             n = int(u["nbytes"])
             if op == ag.AES_OP_CBC_ENC:
@@ -193,8 +193,10 @@ def _check_plan(ag, plan, reqs, tile):
                     low = int.from_bytes(r["iv"][8:].tobytes(), "big")
                     ctr = int(u["w"][2]) | (int(u["w"][3]) << 32)
                     assert ctr == (low + pos // 16) % (1 << 64)
+                elif op in (ag.AES_OP_ECB_ENC, ag.AES_OP_ECB_DEC):
+                    assert not (int(u["meta"]) & (1 << 27)) and not u["w"].any()
                 else:
-                    pred_in = bool(int(u["meta"]) & (1 << 26))
+                    pred_in = bool(int(u["meta"]) & (1 << 27))
                     assert pred_in == (pos > 0)
                     if pos == 0:
                         assert np.array_equal(u["w"].astype("<u4").view(np.uint8), r["iv"])
@@ -202,10 +204,12 @@ def _check_plan(ag, plan, reqs, tile):
             total += n
     assert total == info["payload_bytes"]
     assert len(units) == info["n_units_cbc_dec"] + info["n_units_ctr"] + info["n_chains_cbc_enc"]
-    # order: CBC-dec tiles, CTR tiles, then chains
+    # order: CBC- and ECB-decrypt tiles, CTR tiles, ECB-encrypt tiles, then chains
     k = info["n_units_cbc_dec"]
-    assert (op_of[:k] == ag.AES_OP_CBC_DEC).all()
-    assert (op_of[k:k + info["n_units_ctr"]] == ag.AES_OP_CTR).all()
+    assert np.isin(op_of[:k], (ag.AES_OP_CBC_DEC, ag.AES_OP_ECB_DEC)).all()
+    enc_ops = op_of[k:k + info["n_units_ctr"]]
+    assert np.isin(enc_ops, (ag.AES_OP_CTR, ag.AES_OP_ECB_ENC)).all()
+    assert (np.diff((enc_ops == ag.AES_OP_ECB_ENC).astype(np.int64)) >= 0).all()
     ch = units[k + info["n_units_ctr"]:]
     ch_key = (ch["meta"] & 0xFFFFFF).astype(np.int64)
     assert (np.diff(ch_key) >= 0).all()  # chains grouped by key ...
@@ -213,6 +217,7 @@ def _check_plan(ag, plan, reqs, tile):
         assert (np.diff(ch["nbytes"][ch_key == key].astype(np.int64)) <= 0).all()
     # CTR tiles grouped by key, request order kept within a key
     ctr = units[k:k + info["n_units_ctr"]]
+    ctr = ctr[((ctr["meta"] >> 24) & 7) == ag.AES_OP_CTR]
     key_of = (ctr["meta"] & 0xFFFFFF).astype(np.int64)
     assert (np.diff(key_of) >= 0).all()
     for key in np.unique(key_of):
@@ -247,6 +252,22 @@ def test_plan_ragged_ctr_and_counter_wrap(ag, hctx):
     plan = ag.Plan(hctx, r, 1, off)
     _check_plan(ag, plan, r, 4096)
     plan.close()
+
+
+def test_plan_with_ecb_requests(ag, hctx):
+    wl = workloads.config3(n_reqs=300, max_pages=16)
+    wl.reqs["op"][::5] = ag.AES_OP_ECB_ENC
+    wl.reqs["op"][2::5] = ag.AES_OP_ECB_DEC
+    wl.reqs["length"][::5] = wl.reqs["length"][::5] // 16 * 16
+    wl.reqs["length"][2::5] = wl.reqs["length"][2::5] // 16 * 16
+    plan = ag.Plan(hctx, wl.reqs, wl.keys.shape[0], wl.buf_bytes)
+    _check_plan(ag, plan, wl.reqs, 4096)
+    plan.close()
+    bad = wl.reqs.copy()
+    bad["length"][0] = 4008 + 1
+    with pytest.raises(ag.AesError) as e:
+        ag.Plan(hctx, bad, wl.keys.shape[0], wl.buf_bytes)
+    assert e.value.status == ag.AES_ERR_LENGTH
 
 
 def test_plan_unsorted_requests(ag, hctx):

@@ -220,7 +220,7 @@ def test_errors_and_callbacks(ctx):
         for args, status in (((0, 99, iv, p, q, 4096), a.AES_ERR_RANGE),
                              ((1, 0, iv, p, q, 4008), a.AES_ERR_LENGTH),
                              ((2, 0, iv, p, q, 0), a.AES_ERR_ARG),
-                             ((3, 0, iv, p, q, 4096), a.AES_ERR_ARG),
+                             ((5, 0, iv, p, q, 4096), a.AES_ERR_ARG),
                              ((2, 0, iv, p, p + 16, 4096), a.AES_ERR_OVERLAP)):
             with pytest.raises(a.AesError) as e:
                 s.submit(*args)
