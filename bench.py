@@ -14,6 +14,7 @@ the roofline record of the dominant kernel (HIP events on the launch stream)
 and the CPU oracle timed on a bounded sample of the same workload.
 """
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -46,6 +47,8 @@ def parse():
                     help="measured requests per arrival rate and engine")
     ap.add_argument("--skip-variants", action="store_true",
                     help="skip the table vs bitsliced CTR comparison")
+    ap.add_argument("--skip-e2", action="store_true",
+                    help="skip the single-request ECB size sweep (4 KiB .. 1 MiB)")
     ap.add_argument("--skip-long", action="store_true",
                     help="skip the 8 GiB CTR stream and the 4,096 CBC-encrypt chains")
     ap.add_argument("--skip-batched", action="store_true",
@@ -62,7 +65,7 @@ def cpu_baseline(sample_pages: int):
     import numpy as np
 
     import oracle
-    from synth import workloads
+    from synth import gen, workloads
 
     total = 0
     secs = 0.0
@@ -76,10 +79,19 @@ def cpu_baseline(sample_pages: int):
             threads = oracle.batch(inp, out, wl.reqs, wl.keys, wl.key_bits, n_threads=0)
             secs += time.perf_counter() - t0
             total += wl.payload_bytes()
+    # The size sweep's requests on one core of the oracle (plain scalar C).
+    keys, kb = workloads.make_keys(0, 1, 128)
+    data = gen.bytes_(0, gen.STREAM_DATA, E2_SIZES[-1])
+    e2 = {}
+    for n in E2_SIZES:
+        t0 = time.perf_counter()
+        oracle.mode(oracle.OP_ECB_ENC, keys[0][:16], 128, None, data[:n])
+        e2[str(n)] = round((time.perf_counter() - t0) * 1e6, 1)
     return {"value": round(total / secs / 1e9, 4), "unit": "GB/s", "cores": threads,
             "kind": "oracle",
             "sample": f"first {sample_pages} pages of each of the 4 runs of a step "
-                      f"({total >> 20} MiB), same keys/IVs/bytes, {secs:.1f} s"}
+                      f"({total >> 20} MiB), same keys/IVs/bytes, {secs:.1f} s",
+            "e2_one_core_us": e2}
 
 
 def profiled_traffic(kernel: str, pages: int):
@@ -266,6 +278,147 @@ def bench_long(dev, iters=3):
                                 "one_launch_ms": round(cbc_ms, 3),
                                 "gbs": gbs(wc.buf_bytes, cbc_ms)},
     }
+
+
+E2_SIZES = [4096 << k for k in range(9)]  # 4 KiB .. 1 MiB
+
+
+class _OpenSSLECB:
+    """AES-128-ECB encryption on one host core through the system libcrypto
+    (EVP interface, AES-NI): the modern stand-in for the paper's optimised
+    CPU AES, reported as context -- not the oracle."""
+
+    def __init__(self, key: bytes):
+        import ctypes.util
+
+        name = ctypes.util.find_library("crypto") or "libcrypto.so.3"
+        lib = ctypes.CDLL(name)
+        vp = ctypes.c_void_p
+        lib.EVP_CIPHER_CTX_new.restype = vp
+        lib.EVP_CIPHER_CTX_free.argtypes = [vp]
+        lib.EVP_aes_128_ecb.restype = vp
+        lib.EVP_EncryptInit_ex.argtypes = [vp, vp, vp, vp, vp]
+        lib.EVP_CIPHER_CTX_set_padding.argtypes = [vp, ctypes.c_int]
+        lib.EVP_EncryptUpdate.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int), vp, ctypes.c_int]
+        self.lib = lib
+        self.key = ctypes.create_string_buffer(key, 16)
+        self.ctx = lib.EVP_CIPHER_CTX_new()
+        if lib.EVP_EncryptInit_ex(self.ctx, lib.EVP_aes_128_ecb(), None, self.key, None) != 1:
+            raise OSError("EVP_EncryptInit_ex failed")
+        lib.EVP_CIPHER_CTX_set_padding(self.ctx, 0)
+
+    def encrypt(self, src_ptr: int, dst_ptr: int, n: int):
+        got = ctypes.c_int(0)
+        if self.lib.EVP_EncryptUpdate(self.ctx, dst_ptr, ctypes.byref(got), src_ptr, n) != 1:
+            raise OSError("EVP_EncryptUpdate failed")
+
+    def close(self):
+        self.lib.EVP_CIPHER_CTX_free(self.ctx)
+
+
+def bench_e2(dev, reps=15):
+    """The paper's AES size sweep (section 3.3): one AES-128 ECB-encrypt
+    request of 4 KiB .. 1 MiB with the payload resident on the device, timed
+    on the host clock from the call to the observed completion -- as one
+    kernel launch per request, and through the persistent serving engine --
+    against OpenSSL on one host core (context).  Crossover = the smallest
+    size at which the GPU form is faster."""
+    import numpy as np
+    import torch
+
+    from paper_1305_3345_amd import aesgpu
+    from synth import gen, workloads
+
+    keys, kb = workloads.make_keys(0, 1, 128)
+    nbytes = E2_SIZES[-1]
+    d_in = gen.bytes_torch(0, gen.STREAM_DATA, nbytes, dev)
+    d_out = torch.empty_like(d_in)
+    h_in = d_in.cpu().numpy()
+    h_out = np.empty_like(h_in)
+    stream = torch.cuda.current_stream()
+    ctx = aesgpu.Context(0)
+    sched = aesgpu.expand_keys(keys, kb)
+    d_s = aesgpu.schedules_to_device(sched, dev)
+    cpu = _OpenSSLECB(bytes(keys[0][:16]))
+    med = lambda xs: sorted(xs)[len(xs) // 2]
+    rows = []
+    # One launch per request and the CPU first, with no persistent kernel
+    # resident (its workgroups would hold most compute units' LDS).
+    for n in E2_SIZES:
+        req = np.zeros(1, aesgpu.REQ_DTYPE)
+        req["length"] = n
+        req["op"] = aesgpu.AES_OP_ECB_ENC
+        launch, host = [], []
+        for i in range(reps + 2):
+            t0 = time.perf_counter()
+            aesgpu.request_launch(ctx, d_s, d_in, d_out, req[0], stream=stream)
+            stream.synchronize()
+            t1 = time.perf_counter()
+            cpu.encrypt(h_in.ctypes.data, h_out.ctypes.data, n)
+            t2 = time.perf_counter()
+            if i >= 2:  # the first rounds warm up caches
+                launch.append((t1 - t0) * 1e6)
+                host.append((t2 - t1) * 1e6)
+        rows.append({"bytes": n, "gpu_launch_us": round(med(launch), 1),
+                     "cpu_openssl_us": round(med(host), 1)})
+    with aesgpu.Server(ctx, key_slots=1) as srv:
+        srv.set_key(0, sched[0])
+        for row in rows:
+            n = row["bytes"]
+            persist = []
+            for i in range(reps + 2):
+                t0 = time.perf_counter()
+                srv.wait(srv.submit(aesgpu.AES_OP_ECB_ENC, 0, None, d_in.data_ptr(),
+                                    d_out.data_ptr(), n))
+                if i >= 2:
+                    persist.append((time.perf_counter() - t0) * 1e6)
+            row["gpu_persistent_us"] = round(med(persist), 1)
+    # The paper's E1: an (almost) empty service call -- one 16-byte block --
+    # through persistent kernels of 1,024 and 2,048 threads (two and four
+    # 512-thread workgroups, the smallest grids the two table sets allow) and
+    # the default grid, against one normal kernel launch.
+    req = np.zeros(1, aesgpu.REQ_DTYPE)
+    req["length"] = 16
+    req["op"] = aesgpu.AES_OP_ECB_ENC
+    launch = []
+    for i in range(reps + 2):
+        t0 = time.perf_counter()
+        aesgpu.request_launch(ctx, d_s, d_in, d_out, req[0], stream=stream)
+        stream.synchronize()
+        if i >= 2:
+            launch.append((time.perf_counter() - t0) * 1e6)
+    e1 = {"launch_us": round(med(launch), 1), "persistent_us": {}}
+    for nwg in (2, 4, 0):
+        with aesgpu.Server(ctx, key_slots=1, n_workgroups=nwg) as srv:
+            srv.set_key(0, sched[0])
+            rt = []
+            for i in range(reps + 2):
+                t0 = time.perf_counter()
+                srv.wait(srv.submit(aesgpu.AES_OP_ECB_ENC, 0, None, d_in.data_ptr(),
+                                    d_out.data_ptr(), 16))
+                if i >= 2:
+                    rt.append((time.perf_counter() - t0) * 1e6)
+            label = f"{512 * nwg} threads" if nwg else "default grid"
+            e1["persistent_us"][label] = round(med(rt), 1)
+    cpu.close()
+    ctx.close()
+
+    def crossover(col):
+        for r in rows:
+            if r[col] < r["cpu_openssl_us"]:
+                return r["bytes"]
+        return None
+
+    return {"workload": "one AES-128 ECB-encrypt request per size, payload in HBM, "
+                        f"median of {reps}; CPU: OpenSSL EVP on one core (context, not the oracle)",
+            "sizes": rows,
+            "crossover_bytes_launch": crossover("gpu_launch_us"),
+            "crossover_bytes_persistent": crossover("gpu_persistent_us"),
+            "max_speedup_launch": round(max(r["cpu_openssl_us"] / r["gpu_launch_us"]
+                                            for r in rows), 2),
+            "max_speedup_persistent": round(max(r["cpu_openssl_us"] / r["gpu_persistent_us"]
+                                                for r in rows), 2),
+            "e1_empty_call": e1}
 
 
 def bench_serving(dev, n_measure=2000, n_warm=200):
@@ -481,6 +634,10 @@ def main():
     if not args.skip_long:
         long_stream = bench_long(dev)
 
+    e2 = None
+    if not args.skip_e2:
+        e2 = bench_e2(dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(min(args.cpu_sample_pages, n_pages))
@@ -511,6 +668,7 @@ def main():
         "ctr_variants": variants,
         "batched": batched,
         "long_stream": long_stream,
+        "e2_size_sweep": e2,
         "serving": serving,
     }
     for _, _, plan, _, _, _, _ in runs:

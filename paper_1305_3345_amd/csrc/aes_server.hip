@@ -432,7 +432,8 @@ struct aes_server {
     bool running = false;
     // bookkeeping (under mu)
     std::mutex mu;
-    std::condition_variable cv;
+    std::condition_variable cv;       // completions (waiters)
+    std::condition_variable work_cv;  // submits (the idle completion thread)
     uint64_t next_ticket = 0;
     uint64_t inflight_bytes = 0;
     uint32_t inflight = 0;
@@ -585,7 +586,13 @@ void poll_loop(aes_server *s) {
                 for (int k = 0; k < 16; k++)
                     cpu_relax();
             } else {
-                std::this_thread::sleep_for(std::chrono::microseconds(20));
+                // Idle: sleep until a submit (or shutdown) rather than for a
+                // fixed time, so that the first completion after an idle
+                // period is seen as soon as it lands.
+                std::unique_lock<std::mutex> lk(s->mu);
+                s->work_cv.wait_for(lk, std::chrono::milliseconds(5), [s] {
+                    return !s->live.empty() || s->quit.load(std::memory_order_acquire);
+                });
             }
         }
     }
@@ -686,6 +693,7 @@ int submit_locked(aes_server *s, uint32_t op, uint32_t key_slot, const uint8_t *
     s->inflight_bytes += length;
     s->inflight_units[queue] += units;
     s->live.push_back(ticket);
+    s->work_cv.notify_one();  // the completion thread may be idle
     s->stats.submitted++;
     if (ticket_out)
         *ticket_out = ticket;
@@ -694,7 +702,11 @@ int submit_locked(aes_server *s, uint32_t op, uint32_t key_slot, const uint8_t *
 
 void free_server(aes_server *s) {
     if (s->poller.joinable()) {
-        s->quit.store(true, std::memory_order_release);
+        {
+            std::lock_guard<std::mutex> lk(s->mu);  // no lost wakeup of the idle wait
+            s->quit.store(true, std::memory_order_release);
+        }
+        s->work_cv.notify_all();
         s->poller.join();
     }
     (void)hipSetDevice(s->device);
