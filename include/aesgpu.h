@@ -325,13 +325,27 @@ void aes_graph_destroy(aes_graph_t *graph);
  *     NSK does for services that need more threads.
  *   AES_SERVE_PER_LAUNCH: one kernel launch per request on a pool of
  *     streams (the baseline the paper compares the NSK with).
- * Payloads are device buffers owned by the caller (d_src, d_dst: equal or
- * disjoint); they must stay valid until the request completes.  Admission:
- * at most ring_slots requests and hbm_cap_bytes request bytes in flight;
- * beyond that aes_server_submit returns AES_ERR_AGAIN. */
+ * Payloads are buffers owned by the caller (d_src, d_dst: equal or
+ * disjoint) that must stay valid until the request completes: device memory,
+ * or pinned host memory from aes_server_host_alloc (either side, or both).
+ * Host payloads (the paper's request path of section 3.2, with the pinned
+ * region that section 4 proposes callers allocate in directly):
+ *   persistent engine -- the kernel's waves load the input from and store
+ *     the output to the pinned pages over the host link, so the copy-in,
+ *     rounds and copy-out of different requests overlap with no copy
+ *     commands and no staging;
+ *   per-launch engine -- host_xfer = AES_XFER_COPY (default): each stream
+ *     copies the input into its own HBM staging buffer, launches, and copies
+ *     the output back (three commands in stream order, the traditional way
+ *     the paper measures against); AES_XFER_DIRECT: the launched kernel
+ *     reads and writes the pinned pages as the persistent engine does.
+ *     Requests larger than max_request_bytes always go direct.
+ * Admission: at most ring_slots requests and hbm_cap_bytes request bytes in
+ * flight; beyond that aes_server_submit returns AES_ERR_AGAIN. */
 typedef struct aes_server aes_server_t;
 
 enum { AES_SERVE_PERSISTENT = 0, AES_SERVE_PER_LAUNCH = 1 };
+enum { AES_XFER_COPY = 0, AES_XFER_DIRECT = 1 };
 
 typedef struct aes_server_config {
     uint32_t mode;              /* AES_SERVE_PERSISTENT (default) or AES_SERVE_PER_LAUNCH */
@@ -346,7 +360,10 @@ typedef struct aes_server_config {
                                    (default 1000); the next submit launches it again */
     uint64_t hbm_cap_bytes;     /* admission cap on in-flight request bytes (default 256 MiB) */
     uint64_t max_request_bytes; /* larger requests take a normal launch (default 4 MiB) */
-    uint32_t reserved[8];
+    uint32_t host_xfer;         /* per-launch engine, host payloads: AES_XFER_COPY (default,
+                                   through n_streams HBM staging buffers of max_request_bytes)
+                                   or AES_XFER_DIRECT */
+    uint32_t reserved[7];
 } aes_server_config_t;
 
 /* One completion.  Times: host steady clock in ns (t_submit_ns when the
@@ -382,9 +399,9 @@ int aes_server_set_key(aes_server_t *srv, uint32_t slot, const aes_schedule_t *h
 /* Posts one request (paper section 3.2: buffers, a service request, an
  * optional completion callback).  op and iv as in aes_req_t (iv may be NULL
  * for ECB); length > 0, < 2^32, a multiple of 16 for CBC and ECB.  Sets
- * *ticket.  Errors: AES_ERR_ARG,
- * AES_ERR_LENGTH, AES_ERR_RANGE (key slot), AES_ERR_OVERLAP, AES_ERR_AGAIN
- * (admission), AES_ERR_DEVICE. */
+ * *ticket.  Errors: AES_ERR_ARG, AES_ERR_LENGTH, AES_ERR_RANGE (key slot, or
+ * a range that starts inside a buffer from aes_server_host_alloc and runs
+ * past its end), AES_ERR_OVERLAP, AES_ERR_AGAIN (admission), AES_ERR_DEVICE. */
 int aes_server_submit(aes_server_t *srv, uint32_t op, uint32_t key_slot, const uint8_t iv[16],
                       const uint8_t *d_src, uint8_t *d_dst, uint64_t length, aes_done_cb cb,
                       void *user, uint64_t *ticket);
@@ -404,6 +421,18 @@ int aes_server_replay(aes_server_t *srv, const aes_req_t *reqs, const double *ar
                       uint64_t n, const uint8_t *d_src_base, uint8_t *d_dst_base,
                       aes_done_t *out);
 int aes_server_stats(aes_server_t *srv, aes_server_stats_t *out);
+/* Allocates `bytes` (> 0) of pinned host memory mapped into the server's
+ * device, for request payloads (paper section 4: callers allocate in the
+ * pinned region and save a copy).  *host_ptr is an ordinary host pointer;
+ * pass pointers into the buffer to aes_server_submit or aes_server_replay
+ * (a request's range must lie inside one buffer).  The buffer is owned by
+ * the server: freed by aes_server_host_free or aes_server_destroy.
+ * Errors: AES_ERR_ARG, AES_ERR_NOMEM, AES_ERR_DEVICE. */
+int aes_server_host_alloc(aes_server_t *srv, uint64_t bytes, void **host_ptr);
+/* Frees a buffer from aes_server_host_alloc.  Allowed while nothing is in
+ * flight (else AES_ERR_STATE); AES_ERR_ARG if host_ptr is not such a
+ * buffer's start. */
+int aes_server_host_free(aes_server_t *srv, void *host_ptr);
 /* Waits (up to 10 s) for in-flight requests, stops the kernel and frees
  * everything.  Returns AES_ERR_TIMEOUT if requests were still in flight. */
 int aes_server_destroy(aes_server_t *srv);

@@ -408,12 +408,15 @@ class Graph:
 
 AES_SERVE_PERSISTENT = 0
 AES_SERVE_PER_LAUNCH = 1
+AES_XFER_COPY = 0
+AES_XFER_DIRECT = 1
 
 SERVER_CONFIG_DTYPE = np.dtype([("mode", "<u4"), ("ring_slots", "<u4"), ("key_slots", "<u4"),
                                 ("n_workgroups", "<u4"), ("dec_workgroups", "<u4"),
                                 ("n_streams", "<u4"), ("queue_units", "<u4"),
                                 ("idle_timeout_ms", "<u4"), ("hbm_cap_bytes", "<u8"),
-                                ("max_request_bytes", "<u8"), ("reserved", "<u4", (8,))])
+                                ("max_request_bytes", "<u8"), ("host_xfer", "<u4"),
+                                ("reserved", "<u4", (7,))])
 DONE_DTYPE = np.dtype([("ticket", "<u8"), ("status", "<i4"), ("units", "<u4"),
                        ("t_submit_ns", "<u8"), ("t_done_ns", "<u8"),
                        ("gpu_dispatch_ticks", "<u8"), ("gpu_done_ticks", "<u8")])
@@ -438,6 +441,8 @@ def _server_sig():
             ("aes_server_wait", i32, [p, u64, u64, p]),
             ("aes_server_replay", i32, [p, p, p, u64, p, p, p]),
             ("aes_server_stats", i32, [p, p]),
+            ("aes_server_host_alloc", i32, [p, u64, ctypes.POINTER(p)]),
+            ("aes_server_host_free", i32, [p, p]),
             ("aes_server_destroy", i32, [p])):
         f = getattr(L, name)
         f.restype = res
@@ -465,6 +470,7 @@ class Server:
         self.handle = h.value
         self.ctx = ctx
         self._cbs = {}
+        self._host = {}  # host buffer address -> nbytes
         if _servers is None:
             import atexit
             import weakref
@@ -523,6 +529,21 @@ class Server:
                "aes_server_replay")
         return out
 
+    def host_alloc(self, nbytes: int) -> np.ndarray:
+        """Pinned host buffer mapped into the device (aes_server_host_alloc),
+        as a uint8 numpy array over the library's memory.  Pass it (or
+        slices of it) to submit/replay; it lives until host_free or close."""
+        h = ctypes.c_void_p()
+        _check(lib().aes_server_host_alloc(self.handle, nbytes, ctypes.byref(h)),
+               "aes_server_host_alloc")
+        self._host[h.value] = nbytes
+        return np.ctypeslib.as_array((ctypes.c_uint8 * nbytes).from_address(h.value))
+
+    def host_free(self, buf):
+        addr = _ptr(buf)
+        _check(lib().aes_server_host_free(self.handle, addr), "aes_server_host_free")
+        self._host.pop(addr, None)
+
     def stats(self) -> dict:
         out = np.zeros(len(STATS_NAMES), np.uint64)
         _check(lib().aes_server_stats(self.handle, out.ctypes.data), "aes_server_stats")
@@ -533,6 +554,7 @@ class Server:
             st = lib().aes_server_destroy(self.handle)
             self.handle = None
             self._cbs.clear()
+            self._host.clear()
             _check(st, "aes_server_destroy")
 
     def __enter__(self):

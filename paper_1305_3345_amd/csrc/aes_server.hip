@@ -21,7 +21,17 @@
 // sequence word with a release store; a completion thread watches the
 // completion records (or, in the per-launch engine, HIP events), applies
 // admission accounting, and runs callbacks or queues completions for
-// poll/wait.
+// poll/wait.  Ring positions are numbered apart from tickets: a request that
+// takes a normal launch gets a ticket but no ring position, so the
+// dispatcher, which consumes positions in order, never waits on a gap.
+//
+// Payloads may sit in pinned host buffers that the server allocates and
+// maps into the device (fine-grained, so system-scope fences order them).
+// The persistent kernel reads and writes those pages in place over the host
+// link: its acquire before reading a unit and its release before counting
+// the unit done are system-scope already.  The per-launch engine either does
+// the same or, by default, moves them with copy commands through one HBM
+// staging buffer per stream.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -40,8 +50,8 @@
 
 namespace aesgpu {
 
-// Ring descriptor, 64 bytes, host-mapped.  seq = ticket + 1 once every other
-// field is written.
+// Ring descriptor, 64 bytes, host-mapped.  seq = ring position + 1 once every
+// other field is written.
 struct ServeDesc {
     uint64_t seq;
     uint64_t src;
@@ -55,7 +65,8 @@ struct ServeDesc {
 };
 static_assert(sizeof(ServeDesc) == 64, "descriptor is 64 bytes");
 
-// Completion record, 32 bytes, host-mapped; seq = ticket + 1 written last.
+// Completion record, 32 bytes, host-mapped, in the request's ring slot;
+// seq = ring position + 1 written last.
 struct ServeDone {
     uint64_t seq;
     int32_t status;
@@ -70,7 +81,7 @@ struct ServeUnit {
     Unit u;  // off = the tile's byte position inside the request
     uint64_t src;
     uint64_t dst;
-    uint64_t ticket;
+    uint64_t pos;  // ring position of the request
     uint32_t slot;
     uint32_t reserved;
 };
@@ -88,7 +99,7 @@ struct ServeQueue {
 struct ServeCtl {
     uint32_t stop;  // host -> device
     uint32_t pad0[31];
-    uint64_t consumed;   // device -> host: tickets taken from the ring
+    uint64_t consumed;   // device -> host: ring positions taken
     uint64_t heartbeat;  // device -> host: dispatcher polls
     uint64_t pad1[14];
 };
@@ -103,7 +114,7 @@ struct ServeArgs {
     uint32_t *remaining;  // [ring_slots], device memory
     const aes_schedule_t *keys;
     const uint32_t *timg;
-    uint64_t start_ticket;
+    uint64_t start_pos;
     uint64_t idle_ticks;  // 100 MHz ticks
     uint32_t ring_mask;
     uint32_t qmask;
@@ -118,18 +129,18 @@ struct ServeArgs {
 
 __device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
 
-__device__ __forceinline__ void complete(const ServeArgs &a, uint32_t slot, uint64_t ticket,
+__device__ __forceinline__ void complete(const ServeArgs &a, uint32_t slot, uint64_t pos,
                                          int32_t status) {
     ServeDone *d = a.done + slot;
     __hip_atomic_store(&d->status, status, __ATOMIC_RELAXED, SYS);
     __hip_atomic_store(&d->t_done, now_ticks(), __ATOMIC_RELAXED, SYS);
-    __hip_atomic_store(&d->seq, ticket + 1, __ATOMIC_RELEASE, SYS);
+    __hip_atomic_store(&d->seq, pos + 1, __ATOMIC_RELEASE, SYS);
 }
 
 // The dispatcher: one full wave.
 __device__ void dispatch_loop(const ServeArgs &a) {
     const uint32_t lane = threadIdx.x & 63u;
-    uint64_t next = a.start_ticket;
+    uint64_t next = a.start_pos;
     uint64_t tail[2] = {__hip_atomic_load(&a.q[0].tail, __ATOMIC_RELAXED, AGT),
                         __hip_atomic_load(&a.q[1].tail, __ATOMIC_RELAXED, AGT)};
     uint64_t last_work = now_ticks();
@@ -167,8 +178,8 @@ __device__ void dispatch_loop(const ServeArgs &a) {
                    ((uint64_t)__hip_atomic_load(&d->iv[3], __ATOMIC_RELAXED, SYS) << 32);
         }
         for (uint32_t i = 0; i < n_ready; i++) {
-            const uint64_t ticket = next + i;
-            const uint32_t slot = (uint32_t)(ticket & a.ring_mask);
+            const uint64_t pos = next + i;
+            const uint32_t slot = (uint32_t)(pos & a.ring_mask);
             const uint64_t r_src = __shfl(src, (int)i);
             const uint64_t r_dst = __shfl(dst, (int)i);
             const uint32_t r_len = __shfl(len, (int)i);
@@ -190,7 +201,7 @@ __device__ void dispatch_loop(const ServeArgs &a) {
                             r_src && r_dst;
             if (!ok) {
                 if (lane == 0)
-                    complete(a, slot, ticket, AES_ERR_ARG);
+                    complete(a, slot, pos, AES_ERR_ARG);
                 continue;
             }
             const int qi = op == AES_OP_CBC_DEC || op == AES_OP_ECB_DEC ? 1 : 0;
@@ -204,13 +215,13 @@ __device__ void dispatch_loop(const ServeArgs &a) {
             const uint32_t w2 = (uint32_t)r_ivhi, w3 = (uint32_t)(r_ivhi >> 32);
             for (uint32_t j = lane; j < k; j += 64u) {
                 ServeUnit su;
-                const uint32_t pos = j * a.tile;
-                su.u.off = pos;
-                su.u.nbytes = op == AES_OP_CBC_ENC ? r_len : min(a.tile, r_len - pos);
+                const uint32_t at = j * a.tile;  // the tile's byte offset
+                su.u.off = at;
+                su.u.nbytes = op == AES_OP_CBC_ENC ? r_len : min(a.tile, r_len - at);
                 su.u.meta = key | (op << META_OP_SHIFT);
                 if (op == AES_OP_CTR) {
                     const uint64_t c0 = ((uint64_t)__builtin_bswap32(w2) << 32) | __builtin_bswap32(w3);
-                    const uint64_t c = c0 + pos / 16u;
+                    const uint64_t c = c0 + at / 16u;
                     su.u.w[0] = w0;
                     su.u.w[1] = w1;
                     su.u.w[2] = (uint32_t)c;
@@ -225,7 +236,7 @@ __device__ void dispatch_loop(const ServeArgs &a) {
                 } else {
                     // CBC decryption: the ciphertext block before this tile.
                     const uint4 p =
-                        *reinterpret_cast<const uint4 *>((const uint8_t *)r_src + pos - 16);
+                        *reinterpret_cast<const uint4 *>((const uint8_t *)r_src + at - 16);
                     su.u.w[0] = p.x;
                     su.u.w[1] = p.y;
                     su.u.w[2] = p.z;
@@ -233,7 +244,7 @@ __device__ void dispatch_loop(const ServeArgs &a) {
                 }
                 su.src = r_src;
                 su.dst = r_dst;
-                su.ticket = ticket;
+                su.pos = pos;
                 su.slot = slot;
                 su.reserved = 0;
                 a.qunits[qi][(tail[qi] + j) & a.qmask] = su;
@@ -323,7 +334,7 @@ __device__ void worker_loop(const ServeArgs &a, const uint32_t *lds) {
             un.w[w] = __hip_atomic_load(&p->u.w[w], __ATOMIC_RELAXED, AGT);
         const uint8_t *src = (const uint8_t *)__hip_atomic_load(&p->src, __ATOMIC_RELAXED, AGT);
         uint8_t *dst = (uint8_t *)__hip_atomic_load(&p->dst, __ATOMIC_RELAXED, AGT);
-        const uint64_t ticket = __hip_atomic_load(&p->ticket, __ATOMIC_RELAXED, AGT);
+        const uint64_t pos = __hip_atomic_load(&p->pos, __ATOMIC_RELAXED, AGT);
         const uint32_t slot = __hip_atomic_load(&p->slot, __ATOMIC_RELAXED, AGT);
         const uint32_t op = unit_op(un.meta);
         if (DEC) {
@@ -341,7 +352,7 @@ __device__ void worker_loop(const ServeArgs &a, const uint32_t *lds) {
             left = __hip_atomic_fetch_sub(&a.remaining[slot], 1u, __ATOMIC_ACQ_REL, AGT);
         left = __builtin_amdgcn_readfirstlane(left);
         if (left == 1u && lane == 0)
-            complete(a, slot, ticket, AES_OK);
+            complete(a, slot, pos, AES_OK);
     }
 }
 
@@ -394,8 +405,16 @@ uint64_t host_ns() {
 
 inline void cpu_relax() { __builtin_ia32_pause(); }
 
+// A pinned host buffer from aes_server_host_alloc: host and device views.
+struct HostBuf {
+    uint8_t *h;
+    uint8_t *d;
+    uint64_t n;
+};
+
 struct SlotInfo {
     uint64_t ticket = 0;
+    uint64_t ring_pos = 0;  // persistent engine: the request's ring position
     uint64_t length = 0;
     uint32_t units = 0;  // work units admitted to queue `queue` (persistent engine)
     int queue = 0;
@@ -428,18 +447,22 @@ struct aes_server {
     hipStream_t kstream = nullptr;     // the persistent kernel
     hipStream_t fbstream = nullptr;    // requests that take a normal launch
     std::vector<hipStream_t> streams;  // per-launch engine
-    std::vector<hipEvent_t> events;    // one per ring slot
+    std::vector<uint8_t *> stage;      // per-launch engine: HBM staging, one per stream
+    std::vector<hipEvent_t> events;    // one per ticket slot
     bool running = false;
     // bookkeeping (under mu)
     std::mutex mu;
     std::condition_variable cv;       // completions (waiters)
     std::condition_variable work_cv;  // submits (the idle completion thread)
     uint64_t next_ticket = 0;
+    uint64_t ring_next = 0;          // next ring position (persistent engine)
+    std::vector<uint8_t> ring_busy;  // ring slot holds an unfinished request
     uint64_t inflight_bytes = 0;
     uint32_t inflight = 0;
     uint64_t inflight_units[2] = {0, 0};
     std::vector<SlotInfo> slots;
     std::vector<uint64_t> live;
+    std::vector<HostBuf> hostbufs;
     std::unordered_map<uint64_t, aes_done_t> finished;
     std::deque<uint64_t> finished_order;
     aes_server_stats_t stats{};
@@ -470,7 +493,7 @@ int launch_persistent(aes_server *s) {
     a.remaining = s->remaining_d;
     a.keys = s->keys_d;
     a.timg = s->timg_d;
-    a.start_ticket = __atomic_load_n(&s->ctl->consumed, __ATOMIC_ACQUIRE);
+    a.start_pos = __atomic_load_n(&s->ctl->consumed, __ATOMIC_ACQUIRE);
     a.idle_ticks = (uint64_t)s->cfg.idle_timeout_ms * 100000ull;
     a.ring_mask = s->mask;
     a.qmask = s->cfg.queue_units - 1;
@@ -511,6 +534,8 @@ void finish_slot(aes_server *s, uint32_t slot, int32_t status, uint32_t units, u
     s->inflight--;
     s->inflight_bytes -= si.length;
     s->inflight_units[si.queue] -= si.units;
+    if (!si.by_launch && s->cfg.mode == AES_SERVE_PERSISTENT)
+        s->ring_busy[si.ring_pos & s->mask] = 0;
     s->stats.completed++;
     if (si.cb) {
         cbs.emplace_back(si, d);
@@ -546,12 +571,15 @@ void poll_loop(aes_server *s) {
                         fin = true;
                         st = hip_fail_status(e);
                     }
-                } else if (__atomic_load_n(&s->done[slot].seq, __ATOMIC_ACQUIRE) == t + 1) {
-                    fin = true;
-                    st = s->done[slot].status;
-                    units = s->done[slot].units;
-                    gd = s->done[slot].t_dispatch;
-                    gt = s->done[slot].t_done;
+                } else {
+                    const ServeDone &dr = s->done[si.ring_pos & s->mask];
+                    if (__atomic_load_n(&dr.seq, __ATOMIC_ACQUIRE) == si.ring_pos + 1) {
+                        fin = true;
+                        st = dr.status;
+                        units = dr.units;
+                        gd = dr.t_dispatch;
+                        gt = dr.t_done;
+                    }
                 }
                 if (fin) {
                     finish_slot(s, slot, st, units, gd, gt, cbs);
@@ -571,7 +599,7 @@ void poll_loop(aes_server *s) {
                 last_check = now;
                 if (hipStreamQuery(s->kstream) == hipSuccess) {
                     s->running = false;
-                    if (__atomic_load_n(&s->ctl->consumed, __ATOMIC_ACQUIRE) < s->next_ticket)
+                    if (__atomic_load_n(&s->ctl->consumed, __ATOMIC_ACQUIRE) < s->ring_next)
                         (void)launch_persistent(s);
                 }
             }
@@ -615,19 +643,45 @@ int check_request(aes_server *s, uint32_t op, uint32_t key_slot, const uint8_t *
     return AES_OK;
 }
 
+// Looks [p, p + len) up among the server's host buffers (caller holds mu):
+// returns 1 with *buf set when it starts inside one, 0 when it does not
+// (device memory), AES_ERR_RANGE when it starts inside one and runs past
+// its end.
+int find_host(const aes_server *s, const uint8_t *p, uint64_t len, const HostBuf **buf) {
+    for (const HostBuf &b : s->hostbufs) {
+        if (p >= b.h && p < b.h + b.n) {
+            if (len > (uint64_t)(b.h + b.n - p))
+                return AES_ERR_RANGE;
+            *buf = &b;
+            return 1;
+        }
+    }
+    return 0;
+}
+
 // Posts one request (caller holds mu).
 int submit_locked(aes_server *s, uint32_t op, uint32_t key_slot, const uint8_t *iv,
                   const uint8_t *src, uint8_t *dst, uint64_t length, aes_done_cb cb, void *user,
                   uint64_t t_submit, uint64_t *ticket_out) {
+    const HostBuf *hs = nullptr, *hd = nullptr;
+    const int src_host = find_host(s, src, length, &hs);
+    const int dst_host = find_host(s, dst, length, &hd);
+    if (src_host < 0 || dst_host < 0)
+        return AES_ERR_RANGE;
+    // Device views of the payload (host buffers are mapped into the device).
+    const uint8_t *src_d = src_host ? hs->d + (src - hs->h) : src;
+    uint8_t *dst_d = dst_host ? hd->d + (dst - hd->h) : dst;
     const uint64_t ticket = s->next_ticket;
     const uint32_t slot = (uint32_t)(ticket & s->mask);
-    if (s->slots[slot].busy ||
+    const bool by_launch = s->cfg.mode == AES_SERVE_PER_LAUNCH ||
+                           length > s->cfg.max_request_bytes;
+    const uint64_t ring_pos = s->ring_next;
+    const uint32_t rslot = (uint32_t)(ring_pos & s->mask);
+    if (s->slots[slot].busy || (!by_launch && s->ring_busy[rslot]) ||
         (s->inflight && s->inflight_bytes + length > s->cfg.hbm_cap_bytes)) {
         s->stats.rejected_again++;
         return AES_ERR_AGAIN;
     }
-    const bool by_launch = s->cfg.mode == AES_SERVE_PER_LAUNCH ||
-                           length > s->cfg.max_request_bytes;
     // Units this request adds to its device queue; the queue never holds
     // more than queue_units unconsumed units (see the dispatcher).
     const int queue = op == AES_OP_CBC_DEC || op == AES_OP_ECB_DEC ? 1 : 0;
@@ -647,21 +701,39 @@ int submit_locked(aes_server *s, uint32_t op, uint32_t key_slot, const uint8_t *
             memcpy(r.iv, iv, 16);
         else
             memset(r.iv, 0, 16);
-        hipStream_t st = s->cfg.mode == AES_SERVE_PER_LAUNCH
-                             ? s->streams[ticket % s->streams.size()]
-                             : s->fbstream;
-        int rc = aes_request_launch(s->ctx, s->keys_d, s->cfg.key_slots, src, dst, length, &r, st);
+        const size_t si = s->cfg.mode == AES_SERVE_PER_LAUNCH ? ticket % s->streams.size() : 0;
+        hipStream_t st = s->cfg.mode == AES_SERVE_PER_LAUNCH ? s->streams[si] : s->fbstream;
+        // Copy transport: host sides go through this stream's staging buffer
+        // (in stream order: copy in, rounds in place or into it, copy out).
+        const bool staged = !s->stage.empty() && (src_host || dst_host) &&
+                            length <= s->cfg.max_request_bytes;
+        const uint8_t *ksrc = src_d;
+        uint8_t *kdst = dst_d;
+        hipError_t e;
+        if (staged && src_host) {
+            if ((e = hipMemcpyAsync(s->stage[si], src, length, hipMemcpyHostToDevice, st)) !=
+                hipSuccess)
+                return hip_fail_status(e);
+            ksrc = s->stage[si];
+        }
+        if (staged && dst_host)
+            kdst = s->stage[si];
+        int rc = aes_request_launch(s->ctx, s->keys_d, s->cfg.key_slots, ksrc, kdst, length, &r,
+                                    st);
         if (rc)
             return rc;
-        hipError_t e = hipEventRecord(s->events[slot], st);
-        if (e != hipSuccess)
+        if (staged && dst_host &&
+            (e = hipMemcpyAsync(dst, s->stage[si], length, hipMemcpyDeviceToHost, st)) !=
+                hipSuccess)
+            return hip_fail_status(e);
+        if ((e = hipEventRecord(s->events[slot], st)) != hipSuccess)
             return hip_fail_status(e);
         if (s->cfg.mode == AES_SERVE_PERSISTENT)
             s->stats.fallbacks++;
     } else {
-        ServeDesc *d = s->ring + slot;
-        d->src = (uint64_t)(uintptr_t)src;
-        d->dst = (uint64_t)(uintptr_t)dst;
+        ServeDesc *d = s->ring + rslot;
+        d->src = (uint64_t)(uintptr_t)src_d;
+        d->dst = (uint64_t)(uintptr_t)dst_d;
         d->length = (uint32_t)length;
         d->key_slot = key_slot;
         d->op = op;
@@ -671,7 +743,9 @@ int submit_locked(aes_server *s, uint32_t op, uint32_t key_slot, const uint8_t *
         else
             memset(d->iv, 0, 16);
         d->t_submit = t_submit;
-        __atomic_store_n(&d->seq, ticket + 1, __ATOMIC_RELEASE);
+        __atomic_store_n(&d->seq, ring_pos + 1, __ATOMIC_RELEASE);
+        s->ring_busy[rslot] = 1;
+        s->ring_next++;
         if (!s->running) {
             int rc = launch_persistent(s);
             if (rc)
@@ -680,6 +754,7 @@ int submit_locked(aes_server *s, uint32_t op, uint32_t key_slot, const uint8_t *
     }
     SlotInfo &si = s->slots[slot];
     si.ticket = ticket;
+    si.ring_pos = ring_pos;
     si.length = length;
     si.cb = cb;
     si.user = user;
@@ -728,6 +803,11 @@ void free_server(aes_server *s) {
                     (void *)s->q_d, (void *)s->closed_d, (void *)s->remaining_d})
         if (p)
             (void)hipFree(p);
+    for (uint8_t *p : s->stage)
+        if (p)
+            (void)hipFree(p);
+    for (const HostBuf &b : s->hostbufs)
+        (void)hipHostFree(b.h);
     delete s;
 }
 
@@ -759,7 +839,8 @@ int aes_server_create(aes_ctx_t *ctx, const aes_server_config_t *cfg_in, aes_ser
         cfg.hbm_cap_bytes = 256ull << 20;
     if (!cfg.max_request_bytes)
         cfg.max_request_bytes = 4ull << 20;
-    if (cfg.mode > AES_SERVE_PER_LAUNCH || !pow2(cfg.ring_slots) || cfg.ring_slots < 64 ||
+    if (cfg.mode > AES_SERVE_PER_LAUNCH || cfg.host_xfer > AES_XFER_DIRECT ||
+        !pow2(cfg.ring_slots) || cfg.ring_slots < 64 ||
         cfg.ring_slots > 65536 || cfg.key_slots > 65536 || !pow2(cfg.queue_units) ||
         cfg.queue_units < 1024 || cfg.n_streams > 64 ||
         cfg.max_request_bytes > (uint64_t)(cfg.queue_units) * 4096 ||
@@ -824,12 +905,18 @@ int aes_server_create(aes_ctx_t *ctx, const aes_server_config_t *cfg_in, aes_ser
         s->streams.resize(cfg.n_streams, nullptr);
         for (auto &st2 : s->streams)
             SRV_TRY(hipStreamCreateWithFlags(&st2, hipStreamNonBlocking));
+        if (cfg.host_xfer == AES_XFER_COPY) {
+            s->stage.resize(cfg.n_streams, nullptr);
+            for (auto &p : s->stage)
+                SRV_TRY(hipMalloc((void **)&p, cfg.max_request_bytes));
+        }
     }
     s->events.resize(cfg.ring_slots, nullptr);
     for (auto &ev : s->events)
         SRV_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
 #undef SRV_TRY
     s->slots.resize(cfg.ring_slots);
+    s->ring_busy.assign(cfg.ring_slots, 0);
     s->live.reserve(cfg.ring_slots);
     try {
         s->poller = std::thread(poll_loop, s);
@@ -970,6 +1057,49 @@ int aes_server_stats(aes_server_t *s, aes_server_stats_t *out) {
     out->in_flight = s->inflight;
     out->in_flight_bytes = s->inflight_bytes;
     return AES_OK;
+}
+
+int aes_server_host_alloc(aes_server_t *s, uint64_t bytes, void **host_ptr) {
+    if (!s || !bytes || !host_ptr)
+        return AES_ERR_ARG;
+    *host_ptr = nullptr;
+    std::lock_guard<std::mutex> lk(s->mu);
+    hipError_t e = hipSetDevice(s->device);
+    if (e != hipSuccess)
+        return hip_fail_status(e);
+    HostBuf b;
+    b.n = bytes;
+    if (hipHostMalloc((void **)&b.h, bytes, hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess)
+        return AES_ERR_NOMEM;
+    if ((e = hipHostGetDevicePointer((void **)&b.d, b.h, 0)) != hipSuccess) {
+        (void)hipHostFree(b.h);
+        return hip_fail_status(e);
+    }
+    try {
+        s->hostbufs.push_back(b);
+    } catch (...) {
+        (void)hipHostFree(b.h);
+        return AES_ERR_NOMEM;
+    }
+    *host_ptr = b.h;
+    return AES_OK;
+}
+
+int aes_server_host_free(aes_server_t *s, void *host_ptr) {
+    if (!s || !host_ptr)
+        return AES_ERR_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (size_t i = 0; i < s->hostbufs.size(); i++) {
+        if (s->hostbufs[i].h != host_ptr)
+            continue;
+        if (s->inflight)
+            return AES_ERR_STATE;
+        hipError_t e = hipHostFree(host_ptr);
+        s->hostbufs.erase(s->hostbufs.begin() + (ptrdiff_t)i);
+        return e == hipSuccess ? AES_OK : hip_fail_status(e);
+    }
+    return AES_ERR_ARG;
 }
 
 int aes_server_destroy(aes_server_t *s) {

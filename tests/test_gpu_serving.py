@@ -185,6 +185,30 @@ def test_oversize_request_takes_a_normal_launch(ctx):
         assert first_mismatch(got[o:o + n], oracle_request(wl, r, inp[o:o + n])) is None
 
 
+def test_oversize_between_ring_requests(ctx):
+    """Normal launches interleaved with ring requests: a launched request
+    takes no ring position, so the dispatcher never waits on a gap."""
+    print("[gpu] oversize requests between ring requests", flush=True)
+    wl = make_trace(40, seed=8, sizes=(4, 16, 64, 512))
+    inp = wl.data()
+    d_in = torch.from_numpy(inp).cuda()
+    d_out = torch.empty_like(d_in)
+    sync()
+    big = int((wl.reqs["length"] > (256 << 10)).sum())
+    assert 0 < big < wl.reqs.size
+    with server(ctx, wl, max_request_bytes=256 << 10, ring_slots=64) as s:
+        for rnd in range(3):  # 120 tickets through a 64-slot ring
+            ts = [submit_retry(s, r, d_in.data_ptr() + int(r["offset"]),
+                               d_out.data_ptr() + int(r["offset"])) for r in wl.reqs]
+            for t in ts:
+                assert s.wait(t)["status"] == 0, f"round {rnd}"
+        assert s.stats()["fallbacks"] == 3 * big
+        got = d_out.cpu().numpy()
+    for r in wl.reqs:
+        o, n = int(r["offset"]), int(r["length"])
+        assert first_mismatch(got[o:o + n], oracle_request(wl, r, inp[o:o + n])) is None
+
+
 def test_idle_exit_and_relaunch(ctx):
     print("[gpu] idle exit and relaunch", flush=True)
     wl = make_trace(10, seed=9)
