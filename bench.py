@@ -45,6 +45,8 @@ def parse():
                     help="skip the serving (Poisson arrivals, p50/p99) measurement")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="measured requests per arrival rate and engine")
+    ap.add_argument("--skip-host-serving", action="store_true",
+                    help="skip serving with payloads in pinned host memory")
     ap.add_argument("--skip-variants", action="store_true",
                     help="skip the table vs bitsliced CTR comparison")
     ap.add_argument("--skip-e2", action="store_true",
@@ -495,6 +497,122 @@ def bench_serving(dev, n_measure=2000, n_warm=200):
             "saturation_req_s": sat, "rates": rates}
 
 
+def bench_host_serving(dev, n_measure=1000, n_warm=100, reps=15):
+    """Serving with payloads in pinned host memory (the paper's request path,
+    section 3.2, whose 4 KB measurement includes the copies).  Three
+    transports: the persistent kernel reading and writing the pinned pages
+    directly; one launch per request with copy-in / kernel / copy-out through
+    per-stream HBM staging (the traditional way); one launch per request
+    reading the pages directly.  (1) one request at a time, host clock from
+    submit to observed completion, median of `reps`; (2) a burst of 256
+    AES-128-CTR requests of 1 MiB (GB/s over the host link); (3) the serving
+    trace (Poisson, 4..64 KiB, AES-128-CBC enc/dec) at five rates set by the
+    copy transport's saturated throughput."""
+    import numpy as np
+
+    from paper_1305_3345_amd import aesgpu
+    from synth import gen, workloads
+
+    P, L = aesgpu.AES_SERVE_PERSISTENT, aesgpu.AES_SERVE_PER_LAUNCH
+    transports = {"persistent_direct": dict(mode=P),
+                  "launch_copy": dict(mode=L, host_xfer=aesgpu.AES_XFER_COPY),
+                  "launch_direct": dict(mode=L, host_xfer=aesgpu.AES_XFER_DIRECT)}
+    ctx = aesgpu.Context(0)
+    med = lambda xs: sorted(xs)[len(xs) // 2]
+
+    def make(cfg, scheds, nbytes, data):
+        srv = aesgpu.Server(ctx, key_slots=len(scheds), **cfg)
+        for i, sc in enumerate(scheds):
+            srv.set_key(i, sc)
+        h_in = srv.host_alloc(nbytes)
+        h_out = srv.host_alloc(nbytes)
+        h_in[:] = data[:nbytes]
+        return srv, h_in, h_out
+
+    # (1) and (2): one AES-128 key
+    keys, kb = workloads.make_keys(0, 1, 128)
+    sched = aesgpu.expand_keys(keys, kb)
+    big = 256 << 20
+    data = gen.bytes_(0, gen.STREAM_DATA, big)
+    iv = bytes(16)
+    sizes = [4096, 65536, 1 << 20]
+    rt = {}
+    burst = {}
+    for name, cfg in transports.items():
+        srv, h_in, h_out = make(cfg, sched, big, data)
+        with srv:
+            row = {}
+            for n in sizes:
+                xs = []
+                for i in range(reps + 2):
+                    t0 = time.perf_counter()
+                    srv.wait(srv.submit(aesgpu.AES_OP_CTR, 0, iv, h_in.ctypes.data,
+                                        h_out.ctypes.data, n))
+                    if i >= 2:
+                        xs.append((time.perf_counter() - t0) * 1e6)
+                row[f"{n >> 10}KiB_us"] = round(med(xs), 1)
+            rt[name] = row
+            t0 = time.perf_counter()
+            ts = []
+            for k in range(256):
+                while True:
+                    try:
+                        ts.append(srv.submit(aesgpu.AES_OP_CTR, 0, iv,
+                                             h_in.ctypes.data + k * (1 << 20),
+                                             h_out.ctypes.data + k * (1 << 20), 1 << 20))
+                        break
+                    except aesgpu.AesError as e:
+                        if e.status != aesgpu.AES_ERR_AGAIN:
+                            raise
+            for t in ts:
+                srv.wait(t)
+            burst[name] = round(big / (time.perf_counter() - t0) / 1e9, 2)
+
+    # (3) the serving trace with host payloads
+    n = n_warm + n_measure
+    tr = workloads.config4(1.0, n)
+    nb = (tr.buf_bytes + 7) // 8 * 8
+    tdata = gen.bytes_(0, gen.STREAM_DATA, nb)
+    scheds = aesgpu.expand_keys(tr.keys, tr.key_bits)
+
+    def replay(name, arrivals):
+        srv, h_in, h_out = make(transports[name], scheds, nb, tdata)
+        with srv:
+            done = srv.replay(tr.reqs, arrivals, h_in, h_out)
+        assert (done["status"] == 0).all(), "serving request failed"
+        return done
+
+    def summarize(done):
+        m = done[n_warm:]
+        lat = (m["t_done_ns"].astype(np.int64) - m["t_submit_ns"].astype(np.int64)) / 1e3
+        ops = tr.reqs["op"][n_warm:]
+        out = {"p50_us": round(float(np.percentile(lat, 50)), 1),
+               "p99_us": round(float(np.percentile(lat, 99)), 1)}
+        for op, nm in ((workloads.OP_CBC_ENC, "enc"), (workloads.OP_CBC_DEC, "dec")):
+            sel = lat[ops == op]
+            out[f"{nm}_p50_us"] = round(float(np.percentile(sel, 50)), 1)
+            out[f"{nm}_p99_us"] = round(float(np.percentile(sel, 99)), 1)
+        return out
+
+    sat = {}
+    for name in ("launch_copy", "persistent_direct"):
+        done = replay(name, np.zeros(n))
+        sat[name] = round(n / ((done["t_done_ns"].max() - done["t_submit_ns"].min()) / 1e9), 1)
+    rates = []
+    for frac in (0.1, 0.25, 0.5, 0.75, 0.9):
+        rate = frac * sat["launch_copy"]
+        row = {"fraction_of_launch_copy_saturation": frac, "rate_req_s": round(rate, 1)}
+        for name in ("launch_copy", "persistent_direct"):
+            row[name] = summarize(replay(name, tr.arrivals_s / rate))
+        rates.append(row)
+    ctx.close()
+    return {"workload": "payloads in pinned host memory (aes_server_host_alloc); AES-128",
+            "round_trip_ctr": rt, "burst_256x1MiB_ctr_gbs": burst,
+            "trace": f"{n_measure} measured (+{n_warm} warm-up) requests per rate, Poisson, "
+                     "4..64 KiB, AES-128-CBC enc/dec 50/50, 256 key slots",
+            "saturation_req_s": sat, "rates": rates}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -626,6 +744,10 @@ def main():
     if not args.skip_serving:
         serving = bench_serving(dev, n_measure=args.serve_requests)
 
+    host_serving = None
+    if not args.skip_host_serving:
+        host_serving = bench_host_serving(dev)
+
     batched = None
     if not args.skip_batched:
         batched = bench_batched(dev)
@@ -670,6 +792,7 @@ def main():
         "long_stream": long_stream,
         "e2_size_sweep": e2,
         "serving": serving,
+        "host_serving": host_serving,
     }
     for _, _, plan, _, _, _, _ in runs:
         plan.close()
