@@ -388,6 +388,7 @@ typedef void (*aes_done_cb)(const aes_done_t *done, void *user);
 typedef struct aes_server_stats {
     uint64_t submitted, completed, rejected_again, fallbacks, kernel_launches;
     uint64_t in_flight, in_flight_bytes;
+    uint64_t host_routed; /* requests run on the host route (size-based dispatch) */
 } aes_server_stats_t;
 
 /* cfg may be NULL (defaults).  Errors: AES_ERR_ARG, AES_ERR_DEVICE, AES_ERR_NOMEM. */
@@ -433,6 +434,44 @@ int aes_server_host_alloc(aes_server_t *srv, uint64_t bytes, void **host_ptr);
  * flight (else AES_ERR_STATE); AES_ERR_ARG if host_ptr is not such a
  * buffer's start. */
 int aes_server_host_free(aes_server_t *srv, void *host_ptr);
+
+/* Size-based CPU/GPU dispatch (paper section 4: calling the GPU has a fixed
+ * cost, so small tasks can finish sooner on the CPU; the crossover depends on
+ * the task and the machine and is best measured at start-up).  With a
+ * crossover set for op, aes_server_submit and aes_server_replay run a request
+ * of that op on the host route -- AES-NI on the submitting thread,
+ * aes_host_route_crypt -- when its length is below the crossover, its key
+ * slot has been set, and both its source and destination lie in buffers from
+ * aes_server_host_alloc.  Such a request completes before submit returns
+ * (its callback, if any, runs on the submitting thread).  Every other request
+ * goes to the GPU engine.  Off by default: every crossover is 0.
+ * Errors: AES_ERR_ARG (null server or pointer, op > AES_OP_ECB_DEC). */
+int aes_server_set_crossover(aes_server_t *srv, uint32_t op, uint64_t bytes);
+int aes_server_get_crossover(aes_server_t *srv, uint32_t op, uint64_t *bytes);
+/* Measures the crossovers on this machine and sets them.  For CTR, CBC
+ * decryption and CBC encryption (ECB encryption takes CTR's value, ECB
+ * decryption CBC decryption's): one request at a time at 4 KiB, 8 KiB, ...
+ * up to min(max_request_bytes, 4 MiB) -- 256 KiB for CBC encryption, whose
+ * chain is serial on both sides -- timing the median of 5 round trips
+ * (submit to observed completion) through this server's GPU engine against
+ * the median of 5 host-route runs, with payloads in pinned host buffers and
+ * schedule key_slot (set beforehand).  A crossover is the smallest tested
+ * size from which the GPU engine is faster at every larger tested size, or
+ * UINT64_MAX when it is faster at none (every such request then runs on the
+ * host).  out (may be NULL) receives the five values, indexed by op.  Allowed
+ * while nothing is in flight (else AES_ERR_STATE).  Errors: AES_ERR_ARG,
+ * AES_ERR_RANGE (key slot out of range or never set), AES_ERR_DEVICE (no AES
+ * instructions on the host, or a GPU error), AES_ERR_NOMEM. */
+int aes_server_calibrate(aes_server_t *srv, uint32_t key_slot, uint64_t out[5]);
+
+/* The host route on its own: one request (op and iv as in aes_req_t; iv may
+ * be NULL for ECB) with a host-memory schedule and host-memory payloads
+ * (src == dst, or disjoint), on the calling thread with the CPU's AES
+ * instructions.  Pure host function.  Errors: AES_ERR_ARG, AES_ERR_KEYSIZE
+ * (nr and key_bits not one of 10/128, 12/192, 14/256), AES_ERR_LENGTH,
+ * AES_ERR_OVERLAP, AES_ERR_DEVICE (the CPU has no AES instructions). */
+int aes_host_route_crypt(const aes_schedule_t *sched, uint32_t op, const uint8_t *iv,
+                         const uint8_t *src, uint8_t *dst, uint64_t length);
 /* Waits (up to 10 s) for in-flight requests, stops the kernel and frees
  * everything.  Returns AES_ERR_TIMEOUT if requests were still in flight. */
 int aes_server_destroy(aes_server_t *srv);

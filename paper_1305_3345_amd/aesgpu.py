@@ -406,6 +406,26 @@ class Graph:
 
 # ------------------------------------------------------------------ serving
 
+
+def host_route_crypt(sched, op: int, iv, src: np.ndarray, dst: np.ndarray = None) -> np.ndarray:
+    """aes_host_route_crypt: one request on the host route (the CPU side of
+    size-based dispatch) with a host schedule; dst defaults to a new array,
+    and may be src itself (in place)."""
+    L = lib()
+    f = L.aes_host_route_crypt
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.c_void_p, ctypes.c_uint64]
+    sc = np.ascontiguousarray(np.asarray(sched, dtype=SCHED_DTYPE).reshape(1))
+    src = np.ascontiguousarray(src, dtype=np.uint8)
+    if dst is None:
+        dst = np.empty_like(src)
+    ivb = None if iv is None else np.ascontiguousarray(np.frombuffer(bytes(iv), np.uint8))
+    _check(f(sc.ctypes.data, op, None if ivb is None else ivb.ctypes.data, src.ctypes.data,
+             dst.ctypes.data, src.size), "aes_host_route_crypt")
+    return dst
+
+
 AES_SERVE_PERSISTENT = 0
 AES_SERVE_PER_LAUNCH = 1
 AES_XFER_COPY = 0
@@ -421,7 +441,7 @@ DONE_DTYPE = np.dtype([("ticket", "<u8"), ("status", "<i4"), ("units", "<u4"),
                        ("t_submit_ns", "<u8"), ("t_done_ns", "<u8"),
                        ("gpu_dispatch_ticks", "<u8"), ("gpu_done_ticks", "<u8")])
 STATS_NAMES = ("submitted", "completed", "rejected_again", "fallbacks", "kernel_launches",
-               "in_flight", "in_flight_bytes")
+               "in_flight", "in_flight_bytes", "host_routed")
 assert SERVER_CONFIG_DTYPE.itemsize == 80 and DONE_DTYPE.itemsize == 48
 
 DONE_CB = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
@@ -443,6 +463,9 @@ def _server_sig():
             ("aes_server_stats", i32, [p, p]),
             ("aes_server_host_alloc", i32, [p, u64, ctypes.POINTER(p)]),
             ("aes_server_host_free", i32, [p, p]),
+            ("aes_server_set_crossover", i32, [p, u32, u64]),
+            ("aes_server_get_crossover", i32, [p, u32, ctypes.POINTER(u64)]),
+            ("aes_server_calibrate", i32, [p, u32, p]),
             ("aes_server_destroy", i32, [p])):
         f = getattr(L, name)
         f.restype = res
@@ -543,6 +566,25 @@ class Server:
         addr = _ptr(buf)
         _check(lib().aes_server_host_free(self.handle, addr), "aes_server_host_free")
         self._host.pop(addr, None)
+
+    def set_crossover(self, op: int, nbytes: int):
+        """Size-based dispatch: requests of op shorter than nbytes whose
+        payloads both lie in host buffers of this server run on the host
+        route (0 = never; 2**64 - 1 = always)."""
+        _check(lib().aes_server_set_crossover(self.handle, op, nbytes), "aes_server_set_crossover")
+
+    def get_crossover(self, op: int) -> int:
+        v = ctypes.c_uint64()
+        _check(lib().aes_server_get_crossover(self.handle, op, ctypes.byref(v)),
+               "aes_server_get_crossover")
+        return v.value
+
+    def calibrate(self, key_slot: int = 0) -> np.ndarray:
+        """Measures and sets the five crossovers (aes_server_calibrate); returns them by op."""
+        out = np.zeros(5, np.uint64)
+        _check(lib().aes_server_calibrate(self.handle, key_slot, out.ctypes.data),
+               "aes_server_calibrate")
+        return out
 
     def stats(self) -> dict:
         out = np.zeros(len(STATS_NAMES), np.uint64)

@@ -32,9 +32,15 @@
 // the unit done are system-scope already.  The per-launch engine either does
 // the same or, by default, moves them with copy commands through one HBM
 // staging buffer per stream.
+//
+// Size-based dispatch: with a crossover set for an op, a request of that op
+// below it whose payloads both sit in the server's host buffers runs on the
+// host route (aes_host.cpp) on the submitting thread instead; calibration
+// measures the crossovers with round trips through this server.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -422,7 +428,8 @@ struct SlotInfo {
     void *user = nullptr;
     uint64_t t_submit = 0;
     bool busy = false;
-    bool by_launch = false;  // completion comes from a HIP event
+    bool by_launch = false;   // completion comes from a HIP event
+    bool host_route = false;  // ran on the host route
 };
 
 }  // namespace
@@ -439,6 +446,9 @@ struct aes_server {
     ServeCtl *ctl = nullptr, *ctl_d = nullptr;
     // device memory
     aes_schedule_t *keys_d = nullptr;
+    std::vector<aes_schedule_t> keys_h;  // host copies for the host route
+    std::vector<uint8_t> key_set;
+    uint64_t crossover[5] = {0, 0, 0, 0, 0};  // by op; 0 = never the host route
     ServeUnit *qunits_d[2] = {nullptr, nullptr};
     ServeQueue *q_d = nullptr;
     uint32_t *closed_d = nullptr;
@@ -534,7 +544,7 @@ void finish_slot(aes_server *s, uint32_t slot, int32_t status, uint32_t units, u
     s->inflight--;
     s->inflight_bytes -= si.length;
     s->inflight_units[si.queue] -= si.units;
-    if (!si.by_launch && s->cfg.mode == AES_SERVE_PERSISTENT)
+    if (!si.by_launch && !si.host_route && s->cfg.mode == AES_SERVE_PERSISTENT)
         s->ring_busy[si.ring_pos & s->mask] = 0;
     s->stats.completed++;
     if (si.cb) {
@@ -761,6 +771,7 @@ int submit_locked(aes_server *s, uint32_t op, uint32_t key_slot, const uint8_t *
     si.t_submit = t_submit;
     si.busy = true;
     si.by_launch = by_launch;
+    si.host_route = false;
     si.units = units;
     si.queue = queue;
     s->next_ticket++;
@@ -772,6 +783,58 @@ int submit_locked(aes_server *s, uint32_t op, uint32_t key_slot, const uint8_t *
     s->stats.submitted++;
     if (ticket_out)
         *ticket_out = ticket;
+    return AES_OK;
+}
+
+// The host route (caller does not hold mu).  Returns 1 when the request is
+// not for it (it goes to the GPU engine), else its submit status: AES_OK
+// with *ticket_out set once the request has completed (its own status is in
+// its completion), or AES_ERR_AGAIN when its ticket slot is still busy.
+int try_host_route(aes_server *s, uint32_t op, uint32_t key_slot, const uint8_t *iv,
+                   const uint8_t *src, uint8_t *dst, uint64_t length, aes_done_cb cb,
+                   void *user, uint64_t t_submit, uint64_t *ticket_out) {
+    aes_schedule_t sched;
+    uint64_t ticket;
+    uint32_t slot;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        const HostBuf *b;
+        if (length >= s->crossover[op] || !s->key_set[key_slot] ||
+            find_host(s, src, length, &b) != 1 || find_host(s, dst, length, &b) != 1)
+            return 1;
+        ticket = s->next_ticket;
+        slot = (uint32_t)(ticket & s->mask);
+        SlotInfo &si = s->slots[slot];
+        if (si.busy) {
+            s->stats.rejected_again++;
+            return AES_ERR_AGAIN;
+        }
+        sched = s->keys_h[key_slot];
+        si = SlotInfo();
+        si.ticket = ticket;
+        si.length = length;
+        si.cb = cb;
+        si.user = user;
+        si.t_submit = t_submit;
+        si.busy = true;
+        si.host_route = true;
+        s->next_ticket++;
+        s->inflight++;
+        s->inflight_bytes += length;
+        s->stats.submitted++;
+        s->stats.host_routed++;
+    }
+    const int st = aes_host_route_crypt(&sched, op, iv, src, dst, length);
+    std::vector<std::pair<SlotInfo, aes_done_t>> cbs;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        finish_slot(s, slot, st, 0, 0, 0, cbs);
+    }
+    s->cv.notify_all();
+    if (ticket_out)
+        *ticket_out = ticket;
+    for (auto &c : cbs)
+        c.first.cb(&c.second, c.first.user);
     return AES_OK;
 }
 
@@ -917,6 +980,8 @@ int aes_server_create(aes_ctx_t *ctx, const aes_server_config_t *cfg_in, aes_ser
 #undef SRV_TRY
     s->slots.resize(cfg.ring_slots);
     s->ring_busy.assign(cfg.ring_slots, 0);
+    s->keys_h.assign(cfg.key_slots, aes_schedule_t());
+    s->key_set.assign(cfg.key_slots, 0);
     s->live.reserve(cfg.ring_slots);
     try {
         s->poller = std::thread(poll_loop, s);
@@ -945,6 +1010,8 @@ int aes_server_set_key(aes_server_t *s, uint32_t slot, const aes_schedule_t *hos
     if ((e = hipMemcpy(s->keys_d + slot, host_sched, sizeof(aes_schedule_t),
                        hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail_status(e);
+    s->keys_h[slot] = *host_sched;
+    s->key_set[slot] = 1;
     return AES_OK;
 }
 
@@ -956,10 +1023,14 @@ int aes_server_submit(aes_server_t *s, uint32_t op, uint32_t key_slot, const uin
     int st = check_request(s, op, key_slot, iv, d_src, d_dst, length);
     if (st)
         return st;
+    const uint64_t t_submit = host_ns();
+    st = try_host_route(s, op, key_slot, iv, d_src, d_dst, length, cb, user, t_submit, ticket);
+    if (st != 1)
+        return st;
     std::lock_guard<std::mutex> lk(s->mu);
     if (hipSetDevice(s->device) != hipSuccess)
         return AES_ERR_DEVICE;
-    return submit_locked(s, op, key_slot, iv, d_src, d_dst, length, cb, user, host_ns(), ticket);
+    return submit_locked(s, op, key_slot, iv, d_src, d_dst, length, cb, user, t_submit, ticket);
 }
 
 int aes_server_poll(aes_server_t *s, aes_done_t *out, uint32_t max, uint32_t *n_out) {
@@ -1020,8 +1091,10 @@ int aes_server_replay(aes_server_t *s, const aes_req_t *reqs, const double *arri
         while (host_ns() < target)
             cpu_relax();
         for (;;) {
-            int st;
-            {
+            int st = try_host_route(s, reqs[i].op, reqs[i].key_idx, reqs[i].iv,
+                                    d_src_base + reqs[i].offset, d_dst_base + reqs[i].offset,
+                                    reqs[i].length, nullptr, nullptr, target, &tickets[i]);
+            if (st == 1) {
                 std::lock_guard<std::mutex> lk(s->mu);
                 st = submit_locked(s, reqs[i].op, reqs[i].key_idx, reqs[i].iv,
                                    d_src_base + reqs[i].offset, d_dst_base + reqs[i].offset,
@@ -1100,6 +1173,100 @@ int aes_server_host_free(aes_server_t *s, void *host_ptr) {
         return e == hipSuccess ? AES_OK : hip_fail_status(e);
     }
     return AES_ERR_ARG;
+}
+
+int aes_server_set_crossover(aes_server_t *s, uint32_t op, uint64_t bytes) {
+    if (!s || op > AES_OP_ECB_DEC)
+        return AES_ERR_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->crossover[op] = bytes;
+    return AES_OK;
+}
+
+int aes_server_get_crossover(aes_server_t *s, uint32_t op, uint64_t *bytes) {
+    if (!s || !bytes || op > AES_OP_ECB_DEC)
+        return AES_ERR_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    *bytes = s->crossover[op];
+    return AES_OK;
+}
+
+int aes_server_calibrate(aes_server_t *s, uint32_t key_slot, uint64_t out[5]) {
+    if (!s)
+        return AES_ERR_ARG;
+    if (key_slot >= s->cfg.key_slots)
+        return AES_ERR_RANGE;
+    aes_schedule_t sched;
+    uint64_t saved[5];
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->inflight)
+            return AES_ERR_STATE;
+        if (!s->key_set[key_slot])
+            return AES_ERR_RANGE;
+        sched = s->keys_h[key_slot];
+        memcpy(saved, s->crossover, sizeof(saved));
+        memset(s->crossover, 0, sizeof(s->crossover));  // measure the GPU engine itself
+    }
+    if (!__builtin_cpu_supports("aes"))
+        return AES_ERR_DEVICE;
+    const uint64_t top = std::min<uint64_t>(s->cfg.max_request_bytes, 4ull << 20);
+    uint8_t *in = nullptr, *outb = nullptr;
+    int rc = aes_server_host_alloc(s, top, (void **)&in);
+    if (!rc)
+        rc = aes_server_host_alloc(s, top, (void **)&outb);
+    const uint8_t iv[16] = {0};
+    const uint32_t ops[3] = {AES_OP_CTR, AES_OP_CBC_DEC, AES_OP_CBC_ENC};
+    uint64_t found[3] = {0, 0, 0};
+    constexpr int REPS = 5;
+    for (int oi = 0; oi < 3 && !rc; oi++) {
+        const uint32_t op = ops[oi];
+        const uint64_t cap = op == AES_OP_CBC_ENC ? std::min<uint64_t>(top, 256u << 10) : top;
+        std::vector<uint64_t> sizes;
+        std::vector<bool> gpu_wins;
+        for (uint64_t n = 4096; n <= cap && !rc; n *= 2) {
+            uint64_t tg[REPS + 1], th[REPS + 1];
+            for (int r = 0; r <= REPS && !rc; r++) {  // round 0 warms up
+                uint64_t t0 = host_ns(), ticket = 0;
+                rc = aes_server_submit(s, op, key_slot, iv, in, outb, n, nullptr, nullptr, &ticket);
+                aes_done_t d;
+                if (!rc)
+                    rc = aes_server_wait(s, ticket, 10ull * 1000000000ull, &d);
+                if (!rc)
+                    rc = d.status;
+                tg[r] = host_ns() - t0;
+                t0 = host_ns();
+                if (!rc)
+                    rc = aes_host_route_crypt(&sched, op, iv, in, outb, n);
+                th[r] = host_ns() - t0;
+            }
+            std::sort(tg + 1, tg + REPS + 1);
+            std::sort(th + 1, th + REPS + 1);
+            sizes.push_back(n);
+            gpu_wins.push_back(tg[1 + REPS / 2] < th[1 + REPS / 2]);
+        }
+        if (rc)
+            break;
+        size_t k0 = sizes.size();
+        while (k0 > 0 && gpu_wins[k0 - 1])
+            k0--;
+        found[oi] = k0 == sizes.size() ? UINT64_MAX : sizes[k0];
+    }
+    if (in)
+        (void)aes_server_host_free(s, in);
+    if (outb)
+        (void)aes_server_host_free(s, outb);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (rc) {
+        memcpy(s->crossover, saved, sizeof(saved));
+        return rc;
+    }
+    s->crossover[AES_OP_CTR] = s->crossover[AES_OP_ECB_ENC] = found[0];
+    s->crossover[AES_OP_CBC_DEC] = s->crossover[AES_OP_ECB_DEC] = found[1];
+    s->crossover[AES_OP_CBC_ENC] = found[2];
+    if (out)
+        memcpy(out, s->crossover, sizeof(s->crossover));
+    return AES_OK;
 }
 
 int aes_server_destroy(aes_server_t *s) {
