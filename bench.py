@@ -575,11 +575,15 @@ def bench_host_serving(dev, n_measure=1000, n_warm=100, reps=15):
     tdata = gen.bytes_(0, gen.STREAM_DATA, nb)
     scheds = aesgpu.expand_keys(tr.keys, tr.key_bits)
 
-    def replay(name, arrivals):
+    def replay(name, arrivals, dispatch=False):
         srv, h_in, h_out = make(transports[name], scheds, nb, tdata)
         with srv:
+            cross = srv.calibrate(0) if dispatch else None
             done = srv.replay(tr.reqs, arrivals, h_in, h_out)
+            routed = srv.stats()["host_routed"]
         assert (done["status"] == 0).all(), "serving request failed"
+        if dispatch:
+            return done, cross, routed
         return done
 
     def summarize(done):
@@ -604,13 +608,36 @@ def bench_host_serving(dev, n_measure=1000, n_warm=100, reps=15):
         row = {"fraction_of_launch_copy_saturation": frac, "rate_req_s": round(rate, 1)}
         for name in ("launch_copy", "persistent_direct"):
             row[name] = summarize(replay(name, tr.arrivals_s / rate))
+        # size-based dispatch: the persistent engine after start-up calibration
+        done, cross, routed = replay("persistent_direct", tr.arrivals_s / rate, dispatch=True)
+        row["persistent_dispatch"] = summarize(done)
+        row["persistent_dispatch"]["host_routed_frac"] = round(routed / n, 3)
         rates.append(row)
+    # Size alone ignores load: at rates set by the persistent engine's own
+    # saturation the host route's one submitting core can fall behind.
+    high = []
+    for frac in (0.1, 0.5):
+        rate = frac * sat["persistent_direct"]
+        row = {"fraction_of_persistent_saturation": frac, "rate_req_s": round(rate, 1),
+               "persistent_direct": summarize(replay("persistent_direct", tr.arrivals_s / rate))}
+        done, _, routed = replay("persistent_direct", tr.arrivals_s / rate, dispatch=True)
+        row["persistent_dispatch"] = summarize(done)
+        row["persistent_dispatch"]["host_routed_frac"] = round(routed / n, 3)
+        high.append(row)
+    cross_names = ("cbc_enc", "cbc_dec", "ctr", "ecb_enc", "ecb_dec")
+    crossovers = {nm: (None if int(c) == (1 << 64) - 1 else int(c))
+                  for nm, c in zip(cross_names, cross)}
     ctx.close()
     return {"workload": "payloads in pinned host memory (aes_server_host_alloc); AES-128",
             "round_trip_ctr": rt, "burst_256x1MiB_ctr_gbs": burst,
             "trace": f"{n_measure} measured (+{n_warm} warm-up) requests per rate, Poisson, "
                      "4..64 KiB, AES-128-CBC enc/dec 50/50, 256 key slots",
-            "saturation_req_s": sat, "rates": rates}
+            "saturation_req_s": sat, "rates": rates,
+            "dispatch_crossover_bytes": crossovers, "high_rates": high,
+            "dispatch_note": "persistent_dispatch: aes_server_calibrate at start-up, then requests "
+                             "below their op's crossover run on the host route (AES-NI on the "
+                             "submitting thread); null = the GPU engine was faster at no tested "
+                             "size (4 KiB .. 4 MiB; 256 KiB for CBC encryption)"}
 
 
 def main():
