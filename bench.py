@@ -96,6 +96,11 @@ def cpu_baseline(sample_pages: int):
             "e2_one_core_us": e2}
 
 
+# What the tile kernels are built from (sources and per-file compiler flags).
+TILE_SOURCES = ("csrc/aes_rounds.h", "csrc/internal.h", "csrc/tile_kernel.h",
+                "csrc/aes_tiles_ctr.hip", "csrc/aes_tiles_dec.hip", "build.py")
+
+
 def profiled_traffic(kernel: str, pages: int):
     """HBM bytes per launch of `kernel` on the 65,536-page workload, from the
     committed rocprofv3 counter summary -- or None when the kernel sources
@@ -109,9 +114,9 @@ def profiled_traffic(kernel: str, pages: int):
     if pages != 65536 or not os.path.exists(path):
         return None
     text = open(path).read()
-    m = re.search(r"SHA-1 of `aes_rounds.h` \+ `aes_kernels.hip`\): `([0-9a-f]{40})`", text)
-    src = b"".join(open(os.path.join(here, "paper_1305_3345_amd", "csrc", f), "rb").read()
-                   for f in ("aes_rounds.h", "aes_kernels.hip"))
+    m = re.search(r"Kernel sources at the time \(SHA-1 of [^)]*\): `([0-9a-f]{40})`", text)
+    src = b"".join(open(os.path.join(here, "paper_1305_3345_amd", f), "rb").read()
+                   for f in TILE_SOURCES)
     if not m or hashlib.sha1(src).hexdigest() != m.group(1):
         return None
     m = re.search(r"- `" + re.escape(kernel) + r"`: (\d+)", text)

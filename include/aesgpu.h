@@ -233,7 +233,7 @@ void aes_plan_destroy(aes_plan_t *plan);
 
 /* Kernel shapes of a context; read at every launch (tile_bytes when a plan is
  * created).  Defaults: tile 4096, CTR tiles 2 blocks per lane x 1024 threads,
- * CBC-decrypt tiles 1 block per lane x 1024 threads, chains four lanes each
+ * CBC-decrypt tiles 2 blocks per lane x 1024 threads, chains four lanes each
  * (chain_quad = 1; chain_lanes = 64 when it is 0) x 256 threads, fused kernel
  * 2 blocks per lane, fuse = 1, grid = 0 (one workgroup per compute unit),
  * ctr_variant = AES_CTR_TABLE. */

@@ -257,7 +257,7 @@ struct aes_ctx {
     int next_slot = 0;
     uint32_t tile_bytes = DEFAULT_TILE;
     TileLaunch tile_ctr;
-    TileLaunch tile_dec{1, 1024, 0};  // one block per lane: fewer registers for the 14-round keys
+    TileLaunch tile_dec;
     ChainLaunch chain{256, 64, true, 0};  // four lanes per chain
     int mixed_nb = 2;
     bool fuse = true;        // one launch for batches that mix ops

@@ -1,43 +1,12 @@
-// aes_kernels.hip -- batch kernels (tiles, chains, one fused launch, one
-// request per launch) over the round functions of aes_rounds.h.
+// aes_kernels.hip -- batch kernels (chains, one fused launch, one request per
+// launch) over the round functions of aes_rounds.h.  The tile kernels live in
+// tile_kernel.h, instantiated by aes_tiles_ctr.hip and aes_tiles_dec.hip.
 #include <hip/hip_runtime.h>
 
 #include "aes_rounds.h"
 #include "internal.h"
 
 namespace aesgpu {
-
-// ------------------------------------------------------------ tile kernels
-
-// Parallel-mode kernel: one table set in LDS per workgroup; wave w works
-// units w, w + W, ... (W waves in the grid).
-template <bool DEC, int NB, int WG>
-__global__ __launch_bounds__(WG) void k_tiles(const Unit *__restrict__ units, uint32_t n_units,
-                                              const aes_schedule_t *__restrict__ sched,
-                                              uint32_t n_sched, const uint32_t *__restrict__ timg,
-                                              const uint4 *__restrict__ preds, const uint8_t *in,
-                                              uint8_t *out) {
-    __shared__ uint32_t lds[DEC ? LDS_DEC_WORDS : LDS_ENC_WORDS];
-    fill_tables<DEC>(lds, timg);
-    __syncthreads();
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t L0 = (lane & 31u) << 2;
-    const uint32_t L2 = L0 | SI_BASE;
-    // Waves per workgroup from the template (the kernel is launched with WG
-    // threads), and the wave index and stride made explicitly uniform: the
-    // unit loop, its record and key-schedule loads stay scalar.
-    constexpr uint32_t wpb = WG / 64;
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
-    const uint32_t nw = __builtin_amdgcn_readfirstlane(gridDim.x * wpb);
-    for (uint32_t u = wave; u < n_units; u += nw) {
-        const Unit un = units[u];
-        if (DEC)
-            run_dec_unit<NB>(lds, L0, L2, lane, un, preds ? preds + u : nullptr, sched,
-                             n_sched, in, out);
-        else
-            run_ctr_unit<NB>(lds, L0, lane, un, sched, n_sched, in, out);
-    }
-}
 
 // Wave numbering that spreads consecutive waves over workgroups first.
 __device__ __forceinline__ uint32_t spread_wave(uint32_t wg, uint32_t n_wg) {
@@ -204,66 +173,6 @@ __global__ void k_snapshot_preds(const Unit *__restrict__ units, uint32_t n_unit
 }
 
 // --------------------------------------------------------------- launchers
-
-static int tile_grid(uint32_t n_units, const TileLaunch &cfg, int n_cu) {
-    const int waves = cfg.wg_threads / 64;
-    int grid = cfg.grid > 0 ? cfg.grid : n_cu;
-    const long need = ((long)n_units + waves - 1) / waves;
-    if (need < grid)
-        grid = (int)need;
-    return grid < 1 ? 1 : grid;
-}
-
-using TileKernel = void (*)(const Unit *, uint32_t, const aes_schedule_t *, uint32_t,
-                            const uint32_t *, const uint4 *, const uint8_t *, uint8_t *);
-
-// Compiled shapes: blocks per lane NB in {1, 2, 4} x workgroup size WG in
-// {256, 512, 1024}.  The launch bound sets the VGPR budget (WG 1024 gives
-// 128 VGPRs per lane, 512 gives 256).
-template <bool DEC>
-static TileKernel pick_tile_kernel(int nb, int wg) {
-#define AESGPU_TK(NB_, WG_)                                                                     \
-    if (nb == NB_ && wg <= WG_)                                                                 \
-        return (TileKernel)&k_tiles<DEC, NB_, WG_>;
-    AESGPU_TK(1, 256) AESGPU_TK(1, 512) AESGPU_TK(1, 1024)
-    AESGPU_TK(2, 256) AESGPU_TK(2, 512) AESGPU_TK(2, 1024)
-    AESGPU_TK(4, 256) AESGPU_TK(4, 512)
-#undef AESGPU_TK
-    return nullptr;
-}
-
-bool tile_shape_supported(int nb, int wg) {
-    return wg >= 64 && wg <= 1024 && wg % 64 == 0 && pick_tile_kernel<false>(nb, wg) != nullptr;
-}
-
-static int launch_tiles(TileKernel k, const Unit *d_units, uint32_t n_units,
-                        const aes_schedule_t *d_sched, uint32_t n_sched, const uint32_t *d_timg,
-                        const void *d_preds, const uint8_t *d_in, uint8_t *d_out,
-                        const TileLaunch &cfg, int n_cu, void *stream) {
-    if (!n_units)
-        return hipSuccess;
-    if (!k)
-        return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k, dim3(tile_grid(n_units, cfg, n_cu)), dim3(cfg.wg_threads), 0,
-                       (hipStream_t)stream, d_units, n_units, d_sched, n_sched, d_timg,
-                       (const uint4 *)d_preds, d_in, d_out);
-    return hipGetLastError();
-}
-
-int launch_ctr_tiles(const Unit *d_units, uint32_t n_units, const aes_schedule_t *d_sched,
-                     uint32_t n_sched, const uint32_t *d_timg, const uint8_t *d_in,
-                     uint8_t *d_out, const TileLaunch &cfg, int n_cu, void *stream) {
-    return launch_tiles(pick_tile_kernel<false>(cfg.nb, cfg.wg_threads), d_units, n_units,
-                        d_sched, n_sched, d_timg, nullptr, d_in, d_out, cfg, n_cu, stream);
-}
-
-int launch_cbcdec_tiles(const Unit *d_units, uint32_t n_units, const aes_schedule_t *d_sched,
-                        uint32_t n_sched, const uint32_t *d_timg, const void *d_preds,
-                        const uint8_t *d_in, uint8_t *d_out, const TileLaunch &cfg, int n_cu,
-                        void *stream) {
-    return launch_tiles(pick_tile_kernel<true>(cfg.nb, cfg.wg_threads), d_units, n_units,
-                        d_sched, n_sched, d_timg, d_preds, d_in, d_out, cfg, n_cu, stream);
-}
 
 static uint32_t chain_waves_needed(uint32_t n_chain, uint32_t cl) {
     return (uint32_t)(((uint64_t)n_chain + cl - 1) / cl);
