@@ -144,6 +144,42 @@ bool is_enc_tile_op(uint32_t op) { return op == AES_OP_CTR || op == AES_OP_ECB_E
 
 // Cuts every request into units: CTR, ECB and CBC-decrypt into tile_bytes
 // tiles (a multiple of 16), CBC-encrypt into one chain each.
+// Stable grouping of encryption-side tiles: CTR tiles by key, then ECB
+// tiles by key.  A counting sort over the key indices in use (one pass to
+// count, one to place) when they are dense enough, else a stable sort.
+void group_enc_tiles(std::vector<Unit> &t) {
+    uint32_t max_key = 0;
+    for (const Unit &u : t)
+        max_key = std::max(max_key, u.meta & META_KEY_MASK);
+    auto group = [](const Unit &u) {
+        return ((u.meta & META_KEY_MASK) << 1) | (unit_op(u.meta) == AES_OP_ECB_ENC ? 1u : 0u);
+    };
+    const uint64_t n_groups = 2 * ((uint64_t)max_key + 1);
+    if (n_groups > 4 * (uint64_t)t.size() + 64) {
+        std::stable_sort(t.begin(), t.end(), [&](const Unit &a, const Unit &b) {
+            const uint32_t ea = group(a) & 1u, eb = group(b) & 1u;
+            if (ea != eb)
+                return eb != 0;
+            return (a.meta & META_KEY_MASK) < (b.meta & META_KEY_MASK);
+        });
+        return;
+    }
+    // Slot order: every CTR key first, then every ECB key.
+    auto slot = [&](const Unit &u) {
+        const uint32_t g = group(u);
+        return (g & 1u) * (max_key + 1) + (g >> 1);
+    };
+    std::vector<uint64_t> start(n_groups + 1, 0);
+    for (const Unit &u : t)
+        start[slot(u) + 1]++;
+    for (uint64_t i = 0; i < n_groups; i++)
+        start[i + 1] += start[i];
+    std::vector<Unit> out(t.size());
+    for (const Unit &u : t)
+        out[start[slot(u)]++] = u;
+    t.swap(out);
+}
+
 int plan_units(const aes_req_t *reqs, uint64_t n, uint32_t tile_bytes, Planned &p) {
     try {
         uint64_t n_tiles_ctr = 0, n_tiles_dec = 0, n_chain = 0;
@@ -214,13 +250,7 @@ int plan_units(const aes_req_t *reqs, uint64_t n, uint32_t tile_bytes, Planned &
         // CTR tiles grouped by key (request order kept within a key): the
         // bitsliced kernel shares one key schedule across a wave's 8 tiles.
         // ECB-encrypt tiles follow them (the bitsliced kernel does CTR only).
-        std::stable_sort(p.ctr.begin(), p.ctr.end(), [](const Unit &a, const Unit &b) {
-            const bool ea = unit_op(a.meta) == AES_OP_ECB_ENC;
-            const bool eb = unit_op(b.meta) == AES_OP_ECB_ENC;
-            if (ea != eb)
-                return eb;
-            return (a.meta & META_KEY_MASK) < (b.meta & META_KEY_MASK);
-        });
+        group_enc_tiles(p.ctr);
         // Chains grouped by key, longest first within a key: a wave runs the
         // largest round count among its chains for all of them, so chains
         // that share a key (and so a key size) share waves; and longer

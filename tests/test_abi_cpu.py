@@ -294,3 +294,31 @@ def test_launch_config_validation(ag, hctx):
         assert hctx.get_config() == got  # nothing changes on error
     hctx.set_config(**cfg)
     assert hctx.get_config() == cfg
+
+
+@pytest.mark.parametrize("spread", [8, 200000])
+def test_plan_groups_encryption_tiles_by_key(ag, hctx, spread):
+    """CTR tiles grouped by key (ascending, request order kept within a key),
+    then ECB-encrypt tiles likewise -- with few distinct key indices (the
+    planner's counting sort) and with sparse ones (its stable-sort path)."""
+    r = np.random.default_rng(spread)
+    n = 120
+    reqs = np.zeros(n, workloads.REQ_DTYPE)
+    reqs["length"] = r.integers(1, 5, n) * 4096
+    reqs["offset"][1:] = np.cumsum(reqs["length"])[:-1]
+    reqs["op"] = np.where(r.random(n) < 0.3, ag.AES_OP_ECB_ENC, ag.AES_OP_CTR)
+    keys = r.choice(spread, min(spread, 10), replace=False)
+    reqs["key_idx"] = keys[r.integers(0, keys.size, n)]
+    reqs["iv"] = gen.bytes_(spread, 2, 16 * n).reshape(n, 16)
+    plan = ag.Plan(hctx, reqs, int(keys.max()) + 1, int(reqs["offset"][-1] + reqs["length"][-1]))
+    _check_plan(ag, plan, reqs, 4096)
+    units = plan.units()
+    plan.close()
+    op = (units["meta"] >> 24) & 7
+    key = (units["meta"] & 0xFFFFFF).astype(np.int64)
+    for o in (ag.AES_OP_CTR, ag.AES_OP_ECB_ENC):
+        sel = np.flatnonzero(op == o)
+        assert (np.diff(key[sel]) >= 0).all()
+        for k in np.unique(key[sel]):
+            assert (np.diff(units["offset"][sel][key[sel] == k].astype(np.int64)) > 0).all()
+    assert np.flatnonzero(op == ag.AES_OP_CTR).max() < np.flatnonzero(op == ag.AES_OP_ECB_ENC).min()
