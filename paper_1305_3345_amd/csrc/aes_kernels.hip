@@ -155,9 +155,10 @@ __global__ __launch_bounds__(1024) void k_request(aes_req_t r, uint32_t tile,
     for (uint32_t t = wave; t < n_units; t += nw) {
         const Unit un = request_unit(r, t, tile);
         if (DEC)
-            run_dec_unit<NB>(lds, L0, L2, lane, un, nullptr, sched, n_sched, in, out);
+            run_dec_unit<NB, TILE_NV_DEC>(lds, L0, L2, lane, un, nullptr, sched, n_sched, in,
+                                          out);
         else
-            run_ctr_unit<NB>(lds, L0, lane, un, sched, n_sched, in, out);
+            run_ctr_unit<NB, TILE_NV_CTR>(lds, L0, lane, un, sched, n_sched, in, out);
     }
 }
 

@@ -205,14 +205,48 @@ __device__ __forceinline__ void store_block(uint8_t *dst, uint32_t b, uint32_t n
     }
 }
 
+// ------------------------------------------------------------ round keys
+
+// Round keys of one schedule for the tile loops.  Keys of rounds 1..NV are
+// copied into vector registers once per unit (a DPP move with the identity
+// lane pattern gives the compiler a per-lane value, so it stays in a VGPR);
+// the others are read from the schedule into scalar registers.  With every
+// round key scalar, keys plus the loop state exceed the scalar registers a
+// wave has, and the compiler spills them to VGPR lanes and reads them back
+// with v_readlane inside the rounds.
+template <int NR, int NV>
+struct RoundKeys {
+    static constexpr int V = NV < NR - 1 ? NV : NR - 1;
+    const uint32_t *rk;
+    uint32_t v[V > 0 ? 4 * V : 1];
+    __device__ __forceinline__ explicit RoundKeys(const uint32_t *__restrict__ k) : rk(k) {
+#pragma unroll
+        for (int i = 0; i < 4 * V; i++)
+            v[i] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)k[4 + i], 0xE4, 0xF, 0xF, false);
+    }
+    // Round r's four words (r a compile-time constant after unrolling).
+    __device__ __forceinline__ const uint32_t *operator[](int r) const {
+        return r >= 1 && r <= V ? v + 4 * (r - 1) : rk + 4 * r;
+    }
+};
+
+// Rounds whose keys the 1024-thread tile and per-request kernels hold in
+// vector registers, per side: the fewest that leave no scalar-register spills
+// with two blocks per lane (113 VGPRs for CTR, 103 for decryption, of the 128
+// such workgroups allow).  Measured about 1% faster on every key size and
+// side than all-scalar keys with their spills.
+constexpr int TILE_NV_CTR = 5;
+constexpr int TILE_NV_DEC = 8;
+
 // -------------------------------------------------------------- CTR tiles
 
 // SP 800-38A 6.5: block b of the unit uses counter block nonce || BE64(ctr0 + b).
-template <int NB, int NR>
+template <int NB, int NR, int NV = 0>
 __device__ __forceinline__ void ctr_unit(const uint32_t *lds, uint32_t L0,
                                          uint32_t lane, const Unit &un,
                                          const uint32_t *__restrict__ rk, const uint8_t *in,
                                          uint8_t *out) {
+    const RoundKeys<NR, NV> K(rk);
     const uint32_t nbytes = un.nbytes;
     const uint32_t nblk = (nbytes + 15u) >> 4;
     const uint64_t ctr0 = ((uint64_t)un.w[3] << 32) | un.w[2];
@@ -236,22 +270,23 @@ __device__ __forceinline__ void ctr_unit(const uint32_t *lds, uint32_t L0,
         for (int r = 1; r < NR; r++) {
 #pragma unroll
             for (int i = 0; i < NB; i++)
-                enc_round(lds, s[i], rk + 4 * r, L0);
+                enc_round(lds, s[i], K[r], L0);
         }
 #pragma unroll
         for (int i = 0; i < NB; i++) {
             uint32_t o[4];
-            enc_last(lds, s[i], rk + 4 * NR, L0, x[i], o);
+            enc_last(lds, s[i], K[NR], L0, x[i], o);
             store_block(dst, base + 64u * i + lane, nbytes, o);
         }
     }
 }
 
 // SP 800-38A 6.1: ECB encryption, every block on its own (whole blocks).
-template <int NB, int NR>
+template <int NB, int NR, int NV = 0>
 __device__ __forceinline__ void ecb_enc_unit(const uint32_t *lds, uint32_t L0, uint32_t lane,
                                              const Unit &un, const uint32_t *__restrict__ rk,
                                              const uint8_t *in, uint8_t *out) {
+    const RoundKeys<NR, NV> K(rk);
     const uint32_t nbytes = un.nbytes;
     const uint32_t nblk = nbytes >> 4;
     const uint8_t *src = in + un.off;
@@ -270,12 +305,12 @@ __device__ __forceinline__ void ecb_enc_unit(const uint32_t *lds, uint32_t L0, u
         for (int r = 1; r < NR; r++) {
 #pragma unroll
             for (int i = 0; i < NB; i++)
-                enc_round(lds, s[i], rk + 4 * r, L0);
+                enc_round(lds, s[i], K[r], L0);
         }
 #pragma unroll
         for (int i = 0; i < NB; i++) {
             uint32_t o[4];
-            enc_last(lds, s[i], rk + 4 * NR, L0, zero, o);
+            enc_last(lds, s[i], K[NR], L0, zero, o);
             store_block(dst, base + 64u * i + lane, nbytes, o);
         }
     }
@@ -283,7 +318,7 @@ __device__ __forceinline__ void ecb_enc_unit(const uint32_t *lds, uint32_t L0, u
 
 // Key checks and round-count dispatch for one encryption-table tile (CTR
 // or ECB encryption; wave-uniform).
-template <int NB>
+template <int NB, int NV = 0>
 __device__ __forceinline__ void run_ctr_unit(const uint32_t *lds, uint32_t L0,
                                              uint32_t lane, const Unit &un,
                                              const aes_schedule_t *__restrict__ sched,
@@ -295,19 +330,19 @@ __device__ __forceinline__ void run_ctr_unit(const uint32_t *lds, uint32_t L0,
     const uint32_t nr = ks->nr;
     if (unit_op(un.meta) == AES_OP_ECB_ENC) {
         if (nr == 10)
-            ecb_enc_unit<NB, 10>(lds, L0, lane, un, ks->ek, in, out);
+            ecb_enc_unit<NB, 10, NV>(lds, L0, lane, un, ks->ek, in, out);
         else if (nr == 12)
-            ecb_enc_unit<NB, 12>(lds, L0, lane, un, ks->ek, in, out);
+            ecb_enc_unit<NB, 12, NV>(lds, L0, lane, un, ks->ek, in, out);
         else if (nr == 14)
-            ecb_enc_unit<NB, 14>(lds, L0, lane, un, ks->ek, in, out);
+            ecb_enc_unit<NB, 14, NV>(lds, L0, lane, un, ks->ek, in, out);
         return;
     }
     if (nr == 10)
-        ctr_unit<NB, 10>(lds, L0, lane, un, ks->ek, in, out);
+        ctr_unit<NB, 10, NV>(lds, L0, lane, un, ks->ek, in, out);
     else if (nr == 12)
-        ctr_unit<NB, 12>(lds, L0, lane, un, ks->ek, in, out);
+        ctr_unit<NB, 12, NV>(lds, L0, lane, un, ks->ek, in, out);
     else if (nr == 14)
-        ctr_unit<NB, 14>(lds, L0, lane, un, ks->ek, in, out);
+        ctr_unit<NB, 14, NV>(lds, L0, lane, un, ks->ek, in, out);
 }
 
 // ------------------------------------------------------- CBC-decrypt tiles
@@ -321,11 +356,12 @@ __device__ __forceinline__ uint32_t shift_up(uint32_t old, uint32_t v) {
 // 64i + l; its predecessor is lane l-1's ciphertext, and lane 0 takes lane 63
 // of the previous step (or the block before the unit).  ECB (6.1): P_j =
 // D(C_j), no chaining.
-template <int NB, int NR, bool ECB = false>
+template <int NB, int NR, bool ECB = false, int NV = 0>
 __device__ __forceinline__ void cbcdec_unit(const uint32_t *lds, uint32_t L0,
                                             uint32_t L2, uint32_t lane, const Unit &un,
                                             const uint4 *snap, const uint32_t *__restrict__ dk,
                                             const uint8_t *in, uint8_t *out) {
+    const RoundKeys<NR, NV> K(dk);
     const uint32_t nbytes = un.nbytes;
     const uint32_t nblk = nbytes >> 4;
     const uint8_t *src = in + un.off;
@@ -340,10 +376,13 @@ __device__ __forceinline__ void cbcdec_unit(const uint32_t *lds, uint32_t L0,
         carry[2] = p.z;
         carry[3] = p.w;
     } else {
-        carry[0] = un.w[0];
-        carry[1] = un.w[1];
-        carry[2] = un.w[2];
-        carry[3] = un.w[3];
+        // As values (readfirstlane), not memory: otherwise the compiler merges
+        // this branch and the load above into one load through a selected
+        // pointer, which puts the unit record on the stack.
+        carry[0] = __builtin_amdgcn_readfirstlane(un.w[0]);
+        carry[1] = __builtin_amdgcn_readfirstlane(un.w[1]);
+        carry[2] = __builtin_amdgcn_readfirstlane(un.w[2]);
+        carry[3] = __builtin_amdgcn_readfirstlane(un.w[3]);
     }
     for (uint32_t base = 0; base < nblk; base += 64u * NB) {
         uint32_t c[NB][4], s[NB][4], pred[NB][4];
@@ -374,18 +413,18 @@ __device__ __forceinline__ void cbcdec_unit(const uint32_t *lds, uint32_t L0,
         for (int r = 1; r < NR; r++) {
 #pragma unroll
             for (int i = 0; i < NB; i++)
-                dec_round(lds, s[i], dk + 4 * r, L0);
+                dec_round(lds, s[i], K[r], L0);
         }
 #pragma unroll
         for (int i = 0; i < NB; i++) {
             uint32_t o[4];
-            dec_last(lds, s[i], dk + 4 * NR, L2, pred[i], o);
+            dec_last(lds, s[i], K[NR], L2, pred[i], o);
             store_block(dst, base + 64u * i + lane, nbytes, o);
         }
     }
 }
 
-template <int NB>
+template <int NB, int NV = 0>
 __device__ __forceinline__ void run_dec_unit(const uint32_t *lds, uint32_t L0,
                                              uint32_t L2, uint32_t lane, const Unit &un,
                                              const uint4 *snap,
@@ -398,19 +437,19 @@ __device__ __forceinline__ void run_dec_unit(const uint32_t *lds, uint32_t L0,
     const uint32_t nr = ks->nr;
     if (unit_op(un.meta) == AES_OP_ECB_DEC) {
         if (nr == 10)
-            cbcdec_unit<NB, 10, true>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
+            cbcdec_unit<NB, 10, true, NV>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
         else if (nr == 12)
-            cbcdec_unit<NB, 12, true>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
+            cbcdec_unit<NB, 12, true, NV>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
         else if (nr == 14)
-            cbcdec_unit<NB, 14, true>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
+            cbcdec_unit<NB, 14, true, NV>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
         return;
     }
     if (nr == 10)
-        cbcdec_unit<NB, 10>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
+        cbcdec_unit<NB, 10, false, NV>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
     else if (nr == 12)
-        cbcdec_unit<NB, 12>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
+        cbcdec_unit<NB, 12, false, NV>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
     else if (nr == 14)
-        cbcdec_unit<NB, 14>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
+        cbcdec_unit<NB, 14, false, NV>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
 }
 
 // ------------------------------------------------------- CBC-encrypt chains

@@ -34,10 +34,10 @@ __global__ __launch_bounds__(WG) void k_tiles(const Unit *__restrict__ units, ui
     for (uint32_t u = wave; u < n_units; u += nw) {
         const Unit un = units[u];
         if (DEC)
-            run_dec_unit<NB>(lds, L0, L2, lane, un, preds ? preds + u : nullptr, sched,
-                             n_sched, in, out);
+            run_dec_unit<NB, TILE_NV_DEC>(lds, L0, L2, lane, un, preds ? preds + u : nullptr,
+                                          sched, n_sched, in, out);
         else
-            run_ctr_unit<NB>(lds, L0, lane, un, sched, n_sched, in, out);
+            run_ctr_unit<NB, TILE_NV_CTR>(lds, L0, lane, un, sched, n_sched, in, out);
     }
 }
 
