@@ -69,7 +69,8 @@ struct MixedArgs {
     uint32_t chain_quad;    // 1: 16 chains per wave on four lanes each
 };
 
-// Host-side launchers (aes_kernels.hip).  Each returns a hipError_t value.
+// Host-side launchers.  Each returns a hipError_t value.  Tile kernels:
+// aes_tiles_ctr.hip and aes_tiles_dec.hip; the others: aes_kernels.hip.
 int launch_ctr_tiles(const Unit *d_units, uint32_t n_units, const aes_schedule_t *d_sched,
                      uint32_t n_sched, const uint32_t *d_timg, const uint8_t *d_in,
                      uint8_t *d_out, const TileLaunch &cfg, int n_cu, void *stream);
