@@ -235,7 +235,7 @@ void aes_plan_destroy(aes_plan_t *plan);
  * created).  Defaults: tile 4096, CTR tiles 2 blocks per lane x 1024 threads,
  * CBC-decrypt tiles 2 blocks per lane x 1024 threads, chains four lanes each
  * (chain_quad = 1; chain_lanes = 64 when it is 0) x 256 threads, fused kernel
- * 2 blocks per lane, fuse = 1, grid = 0 (one workgroup per compute unit),
+ * 1 block per lane, fuse = 1, grid = 0 (one workgroup per compute unit),
  * ctr_variant = AES_CTR_TABLE. */
 typedef struct aes_launch_config {
     uint32_t tile_bytes;  /* bytes per CTR / CBC-decrypt unit: multiple of 1024 */
@@ -246,7 +246,9 @@ typedef struct aes_launch_config {
     uint32_t chain_lanes; /* CBC-encrypt: chains (active lanes) per wave, 1..64 */
     uint32_t chain_wg;    /* CBC-encrypt chain kernel: threads per workgroup */
     uint32_t mixed_nb;    /* fused mixed-batch kernel: blocks per lane (1, 2) */
-    uint32_t fuse;        /* 1: a batch mixing ops runs as one launch; 0: one launch per op */
+    uint32_t fuse;        /* 1: a batch mixing CBC-encrypt chains with tiles runs as one launch
+                             (batches without chains always run one launch per table set);
+                             0: one launch per op */
     uint32_t grid;        /* workgroups of tile and fused kernels; 0 = one per compute unit */
     uint32_t ctr_variant; /* CTR units of batches and plans: AES_CTR_TABLE or AES_CTR_BITSLICE */
     uint32_t chain_quad;  /* CBC-encrypt chains: 0 = chain_lanes chains per wave, one lane each;
@@ -270,11 +272,11 @@ int aes_ctx_set_config(aes_ctx_t *ctx, const aes_launch_config_t *cfg);
 
 /* Autotuner: times plan launches of reqs on the caller's buffers (d_in must
  * differ from d_out; d_out is overwritten with the batch's result) for tile
- * sizes, tile-kernel shapes, chain lanes or four-lane chains, the fusion
- * switch and (for batches with CTR requests) the CTR variant by coordinate
- * descent (median of iters launches each), leaves the fastest configuration
- * set in ctx and copies it to *best (may be NULL).  Plans created afterwards
- * use its tile size.  Errors: as aes_batch; AES_ERR_OVERLAP if d_in == d_out. */
+ * sizes, tile-kernel shapes, the fused kernel's blocks per lane, chain lanes
+ * or four-lane chains, the fusion switch and (for batches with CTR requests)
+ * the CTR variant by coordinate descent (median of iters launches each),
+ * leaves the fastest configuration set in ctx and copies it to *best (may be
+ * NULL).  Plans created afterwards use its tile size.  Errors: as aes_batch; AES_ERR_OVERLAP if d_in == d_out. */
 int aes_tune(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_scheds,
              uint64_t buf_bytes, const aes_schedule_t *d_scheds, const uint8_t *d_in,
              uint8_t *d_out, uint32_t iters, aes_launch_config_t *best);

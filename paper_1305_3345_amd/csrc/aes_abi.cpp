@@ -289,7 +289,7 @@ struct aes_ctx {
     TileLaunch tile_ctr;
     TileLaunch tile_dec;
     ChainLaunch chain{256, 64, true, 0};  // four lanes per chain
-    int mixed_nb = 2;
+    int mixed_nb = 1;        // fused kernel: 1 block per lane (its chain path takes the VGPRs)
     bool fuse = true;        // one launch for batches that mix ops
     int grid = 0;            // tile / fused kernel workgroups, 0 = one per compute unit
     uint32_t ctr_variant = AES_CTR_TABLE;
@@ -382,7 +382,11 @@ int launch_planned(aes_ctx *ctx, const PlanView &v, const aes_schedule_t *d_sche
         u_ctr += n_ctr_only;
     const size_t n_ctr_tab = bitslice ? v.n_ecb : v.n_ctr;
     const int kinds = (v.n_dec > 0) + (n_ctr_tab > 0) + (v.n_chain > 0);
-    if (ctx->fuse && kinds > 1) {
+    // One fused launch when CBC-encrypt chains share the batch with tiles: the
+    // long chains then run beside the tiles on the workgroups the split gives
+    // them.  Without chains, one launch per table set is faster (the tile
+    // kernels carry no chain registers).
+    if (ctx->fuse && v.n_chain > 0 && kinds > 1) {
         const int grid = ctx->grid > 0 ? ctx->grid : ctx->n_cu;
         MixedArgs a;
         a.dec = u_dec;
@@ -1091,10 +1095,11 @@ int aes_tune(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_
         c = best;
         c.ctr_nb = c.dec_nb = sh[0];
         c.ctr_wg = c.dec_wg = sh[1];
-        if (c.mixed_nb != 1 && sh[0] == 1)
-            c.mixed_nb = 1;
-        else if (sh[0] >= 2)
-            c.mixed_nb = 2;
+        st = trial(c);
+    }
+    for (uint32_t mnb = 1; mnb <= 2 && !st; mnb++) {
+        c = best;
+        c.mixed_nb = mnb;
         st = trial(c);
     }
     const uint32_t lanes[] = {16, 32, 64};

@@ -74,6 +74,8 @@ def test_chains_on_four_lanes(fresh, fuse):
 
 @pytest.mark.parametrize("ops", [(0, 1), (0, 2), (1, 2), (0,), (1,), (2,)])
 def test_fused_kernel_op_subsets(fresh, ops):
+    """Subsets with CBC-encrypt chains run fused; (1, 2) has none and runs as
+    one launch per table set."""
     print(f"[gpu] op subset {ops}", flush=True)
     wl = mixed_workload(n=160, max_pages=6)
     r = np.random.default_rng(len(ops)).integers(0, len(ops), wl.reqs.size)
