@@ -221,10 +221,12 @@ int aes_plan_create(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint
 int aes_plan_launch(aes_plan_t *plan, const aes_schedule_t *d_scheds, const uint8_t *d_in,
                     uint8_t *d_out, void *stream);
 int aes_plan_info(const aes_plan_t *plan, aes_plan_info_t *info);
-/* Copies up to max unit records (CBC- and ECB-decrypt tiles, then CTR tiles
- * grouped by key, then ECB-encrypt tiles grouped by key, then chains grouped
- * by key, longest first within a key) to out and sets *n_out to the plan's
- * total unit count. */
+/* Copies up to max unit records (CBC- and ECB-decrypt tiles in request order,
+ * then CTR tiles, then ECB-encrypt tiles, then chains grouped by key, longest
+ * first within a key) to out and sets *n_out to the plan's total unit count.
+ * CTR and ECB-encrypt tiles are in request order, or, when the context's CTR
+ * variant was AES_CTR_BITSLICE at planning time, grouped by key with request
+ * order kept within a key. */
 int aes_plan_units(const aes_plan_t *plan, aes_unit_t *out, uint64_t max, uint64_t *n_out);
 /* Waits for the device to be idle, then frees the plan.  NULL is a no-op. */
 void aes_plan_destroy(aes_plan_t *plan);

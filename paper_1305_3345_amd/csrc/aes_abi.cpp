@@ -137,50 +137,61 @@ struct Planned {
     uint64_t dec_bytes = 0, ctr_bytes = 0, chain_bytes = 0;
     bool dec_has_pred_in = false;
     size_t n_ecb = 0;  // ECB-encrypt tiles at the end of ctr
+    std::vector<Unit> ecb;       // ECB-encrypt tiles while planning (appended to ctr)
+    std::vector<Unit> sort_buf;  // scratch of the key grouping
+
+    // Empties the plan and keeps the vectors' storage: a context reuses one
+    // Planned for every single-call batch, so a call touches no fresh pages.
+    void reset() {
+        dec.clear();
+        ctr.clear();
+        ecb.clear();
+        chains.clear();
+        payload = extent = 0;
+        dec_bytes = ctr_bytes = chain_bytes = 0;
+        dec_has_pred_in = false;
+        n_ecb = 0;
+    }
 };
 
 bool is_dec_tile_op(uint32_t op) { return op == AES_OP_CBC_DEC || op == AES_OP_ECB_DEC; }
 bool is_enc_tile_op(uint32_t op) { return op == AES_OP_CTR || op == AES_OP_ECB_ENC; }
 
-// Cuts every request into units: CTR, ECB and CBC-decrypt into tile_bytes
-// tiles (a multiple of 16), CBC-encrypt into one chain each.
-// Stable grouping of encryption-side tiles: CTR tiles by key, then ECB
-// tiles by key.  A counting sort over the key indices in use (one pass to
-// count, one to place) when they are dense enough, else a stable sort.
-void group_enc_tiles(std::vector<Unit> &t) {
+// Stable grouping of tiles by key index.  A counting sort over the key
+// indices in use (one pass to count, one to place; buf is scratch) when they
+// are dense enough, else a stable sort.
+void group_by_key(std::vector<Unit> &t, std::vector<Unit> &buf) {
     uint32_t max_key = 0;
     for (const Unit &u : t)
         max_key = std::max(max_key, u.meta & META_KEY_MASK);
-    auto group = [](const Unit &u) {
-        return ((u.meta & META_KEY_MASK) << 1) | (unit_op(u.meta) == AES_OP_ECB_ENC ? 1u : 0u);
-    };
-    const uint64_t n_groups = 2 * ((uint64_t)max_key + 1);
-    if (n_groups > 4 * (uint64_t)t.size() + 64) {
-        std::stable_sort(t.begin(), t.end(), [&](const Unit &a, const Unit &b) {
-            const uint32_t ea = group(a) & 1u, eb = group(b) & 1u;
-            if (ea != eb)
-                return eb != 0;
+    const uint64_t n_keys = (uint64_t)max_key + 1;
+    if (n_keys > 4 * (uint64_t)t.size() + 64) {
+        std::stable_sort(t.begin(), t.end(), [](const Unit &a, const Unit &b) {
             return (a.meta & META_KEY_MASK) < (b.meta & META_KEY_MASK);
         });
         return;
     }
-    // Slot order: every CTR key first, then every ECB key.
-    auto slot = [&](const Unit &u) {
-        const uint32_t g = group(u);
-        return (g & 1u) * (max_key + 1) + (g >> 1);
-    };
-    std::vector<uint64_t> start(n_groups + 1, 0);
+    std::vector<uint64_t> start(n_keys + 1, 0);
     for (const Unit &u : t)
-        start[slot(u) + 1]++;
-    for (uint64_t i = 0; i < n_groups; i++)
+        start[(u.meta & META_KEY_MASK) + 1]++;
+    for (uint64_t i = 0; i < n_keys; i++)
         start[i + 1] += start[i];
-    std::vector<Unit> out(t.size());
+    buf.resize(t.size());
     for (const Unit &u : t)
-        out[start[slot(u)]++] = u;
-    t.swap(out);
+        buf[start[u.meta & META_KEY_MASK]++] = u;
+    t.swap(buf);
 }
 
-int plan_units(const aes_req_t *reqs, uint64_t n, uint32_t tile_bytes, Planned &p) {
+// Cuts every request into units: CTR, ECB and CBC-decrypt into tile_bytes
+// tiles (a multiple of 16), CBC-encrypt into one chain each.  p is emptied
+// first (its storage kept).  Encryption-side tiles: CTR tiles, then
+// ECB-encrypt tiles (the bitsliced kernel takes only the CTR range); with
+// group_keys each of the two groups is ordered by key (request order kept
+// within a key), which the bitsliced kernel needs to share one schedule
+// across a wave's tiles -- the table kernels read a schedule per tile.
+int plan_units(const aes_req_t *reqs, uint64_t n, uint32_t tile_bytes, bool group_keys,
+               Planned &p) {
+    p.reset();
     try {
         uint64_t n_tiles_ctr = 0, n_tiles_dec = 0, n_chain = 0;
         for (uint64_t i = 0; i < n; i++) {
@@ -231,9 +242,7 @@ int plan_units(const aes_req_t *reqs, uint64_t n, uint32_t tile_bytes, Planned &
                     p.ctr.push_back(u);
                 } else if (r.op == AES_OP_ECB_ENC || r.op == AES_OP_ECB_DEC) {
                     u.w[0] = u.w[1] = u.w[2] = u.w[3] = 0;  // every block on its own
-                    (r.op == AES_OP_ECB_ENC ? p.ctr : p.dec).push_back(u);
-                    if (r.op == AES_OP_ECB_ENC)
-                        p.n_ecb++;
+                    (r.op == AES_OP_ECB_ENC ? p.ecb : p.dec).push_back(u);
                 } else {
                     if (pos == 0) {
                         for (int w = 0; w < 4; w++)
@@ -247,10 +256,12 @@ int plan_units(const aes_req_t *reqs, uint64_t n, uint32_t tile_bytes, Planned &
                 }
             }
         }
-        // CTR tiles grouped by key (request order kept within a key): the
-        // bitsliced kernel shares one key schedule across a wave's 8 tiles.
-        // ECB-encrypt tiles follow them (the bitsliced kernel does CTR only).
-        group_enc_tiles(p.ctr);
+        if (group_keys) {
+            group_by_key(p.ctr, p.sort_buf);
+            group_by_key(p.ecb, p.sort_buf);
+        }
+        p.n_ecb = p.ecb.size();
+        p.ctr.insert(p.ctr.end(), p.ecb.begin(), p.ecb.end());
         // Chains grouped by key, longest first within a key: a wave runs the
         // largest round count among its chains for all of them, so chains
         // that share a key (and so a key size) share waves; and longer
@@ -294,6 +305,11 @@ struct aes_ctx {
     int grid = 0;            // tile / fused kernel workgroups, 0 = one per compute unit
     uint32_t ctr_variant = AES_CTR_TABLE;
     hipStream_t capture = nullptr;  // private stream for graph capture and tuning
+    // Scratch of the single-call forms, reused from call to call (a context
+    // is used by one thread at a time): requests built from the caller's
+    // arrays, and the plan of the batch.
+    std::vector<aes_req_t> scratch_reqs;
+    Planned scratch_plan;
 };
 
 struct aes_graph {
@@ -446,8 +462,8 @@ int run_batch(aes_ctx *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
         return st;
     if ((st = validate(reqs, n, n_scheds, buf_bytes)))
         return st;
-    Planned p;
-    if ((st = plan_units(reqs, n, ctx->tile_bytes, p)))
+    Planned &p = ctx->scratch_plan;
+    if ((st = plan_units(reqs, n, ctx->tile_bytes, ctx->ctr_variant == AES_CTR_BITSLICE, p)))
         return st;
     if (!p.payload)
         return AES_OK;
@@ -500,7 +516,7 @@ int single_mode(uint32_t op, aes_ctx *ctx, const aes_schedule_t *d_scheds, uint3
     const bool ecb = op == AES_OP_ECB_ENC || op == AES_OP_ECB_DEC;  // no IVs
     if (n && (!offsets || !lengths || !key_idx || (!ivs && !ecb)))
         return AES_ERR_ARG;
-    std::vector<aes_req_t> reqs;
+    std::vector<aes_req_t> &reqs = ctx->scratch_reqs;
     try {
         reqs.resize(n);
     } catch (const std::bad_alloc &) {
@@ -683,7 +699,8 @@ int aes_plan_create(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n, uint32_t 
     pl->tile_bytes = ctx->tile_bytes;
     pl->n_scheds = n_scheds;
     pl->buf_bytes = buf_bytes;
-    if ((st = plan_units(reqs, n, ctx->tile_bytes, pl->p))) {
+    if ((st = plan_units(reqs, n, ctx->tile_bytes, ctx->ctr_variant == AES_CTR_BITSLICE,
+                         pl->p))) {
         delete pl;
         return st;
     }
@@ -1052,19 +1069,21 @@ int aes_tune(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_
     aes_launch_config_t best;
     aes_ctx_get_config(ctx, &best);
     double best_ms = 1e30;
-    // One candidate: set it, (re)plan when the tile size changed, time it.
+    // One candidate: set it, (re)plan when the tile size or the CTR variant
+    // (which decides the key grouping of CTR tiles) changed, time it.
     aes_plan *plan = nullptr;
-    uint32_t plan_tile = 0;
+    uint32_t plan_tile = 0, plan_variant = 0;
     auto trial = [&](const aes_launch_config_t &c) -> int {
         int s2 = aes_ctx_set_config(ctx, &c);
         if (s2)
             return AES_OK;  // shape not available: skip
-        if (!plan || plan_tile != c.tile_bytes) {
+        if (!plan || plan_tile != c.tile_bytes || plan_variant != c.ctr_variant) {
             aes_plan_destroy(plan);
             plan = nullptr;
             if ((s2 = aes_plan_create(ctx, reqs, n_reqs, n_scheds, buf_bytes, &plan)))
                 return s2;
             plan_tile = c.tile_bytes;
+            plan_variant = c.ctr_variant;
         }
         double ms = 0;
         if ((s2 = time_plan(plan, d_scheds, d_in, d_out, (int)iters, &ms)))

@@ -161,7 +161,7 @@ def test_single_mode_entry_points_validate(ag, hctx):
 
 # ------------------------------------------------------------------- planner
 
-def _check_plan(ag, plan, reqs, tile):
+def _check_plan(ag, plan, reqs, tile, grouped=False):
     units = plan.units()
     info = plan.info()
     assert info["payload_bytes"] == int(reqs["length"].sum())
@@ -215,15 +215,22 @@ def _check_plan(ag, plan, reqs, tile):
     assert (np.diff(ch_key) >= 0).all()  # chains grouped by key ...
     for key in np.unique(ch_key):  # ... longest first within a key
         assert (np.diff(ch["nbytes"][ch_key == key].astype(np.int64)) <= 0).all()
-    # CTR tiles grouped by key, request order kept within a key
-    ctr = units[k:k + info["n_units_ctr"]]
-    ctr = ctr[((ctr["meta"] >> 24) & 7) == ag.AES_OP_CTR]
-    key_of = (ctr["meta"] & 0xFFFFFF).astype(np.int64)
-    assert (np.diff(key_of) >= 0).all()
-    for key in np.unique(key_of):
-        mine = ctr[key_of == key]
-        assert (np.diff(mine["offset"].astype(np.int64)) > 0).all() or \
-            not np.array_equal(np.sort(reqs["offset"]), reqs["offset"])
+    # CTR tiles, then ECB-encrypt tiles: each group in request order, or
+    # (grouped) by key with request order kept within a key
+    enc = units[k:k + info["n_units_ctr"]]
+    order = np.argsort(reqs["offset"], kind="stable")
+    for o in (ag.AES_OP_CTR, ag.AES_OP_ECB_ENC):
+        mine = enc[((enc["meta"] >> 24) & 7) == o]
+        # index of each tile's request in the caller's order
+        pos = np.searchsorted(reqs["offset"][order], mine["offset"], side="right") - 1
+        req_of = order[pos].astype(np.int64)
+        key_of = (mine["meta"] & 0xFFFFFF).astype(np.int64)
+        if grouped:
+            assert (np.diff(key_of) >= 0).all()
+            for key in np.unique(key_of):
+                assert (np.diff(req_of[key_of == key]) >= 0).all()
+        else:
+            assert (np.diff(req_of) >= 0).all()
 
 
 def test_plan_covers_config3_batch(ag, hctx):
@@ -296,10 +303,12 @@ def test_launch_config_validation(ag, hctx):
     assert hctx.get_config() == cfg
 
 
+@pytest.mark.parametrize("variant", ["table", "bitslice"])
 @pytest.mark.parametrize("spread", [8, 200000])
-def test_plan_groups_encryption_tiles_by_key(ag, hctx, spread):
-    """CTR tiles grouped by key (ascending, request order kept within a key),
-    then ECB-encrypt tiles likewise -- with few distinct key indices (the
+def test_plan_orders_encryption_tiles(ag, hctx, spread, variant):
+    """CTR tiles, then ECB-encrypt tiles: in request order under the table
+    variant; grouped by key (ascending, request order kept within a key)
+    under the bitsliced variant -- with few distinct key indices (the
     planner's counting sort) and with sparse ones (its stable-sort path)."""
     r = np.random.default_rng(spread)
     n = 120
@@ -310,15 +319,13 @@ def test_plan_groups_encryption_tiles_by_key(ag, hctx, spread):
     keys = r.choice(spread, min(spread, 10), replace=False)
     reqs["key_idx"] = keys[r.integers(0, keys.size, n)]
     reqs["iv"] = gen.bytes_(spread, 2, 16 * n).reshape(n, 16)
-    plan = ag.Plan(hctx, reqs, int(keys.max()) + 1, int(reqs["offset"][-1] + reqs["length"][-1]))
-    _check_plan(ag, plan, reqs, 4096)
+    perm = r.permutation(n)  # callers' order need not be offset order
+    reqs = reqs[perm]
+    v = ag.AES_CTR_BITSLICE if variant == "bitslice" else ag.AES_CTR_TABLE
+    hctx.set_config(ctr_variant=v)
+    plan = ag.Plan(hctx, reqs, int(keys.max()) + 1, int(reqs["offset"].max() + 4 * 4096))
+    _check_plan(ag, plan, reqs, 4096, grouped=variant == "bitslice")
     units = plan.units()
     plan.close()
     op = (units["meta"] >> 24) & 7
-    key = (units["meta"] & 0xFFFFFF).astype(np.int64)
-    for o in (ag.AES_OP_CTR, ag.AES_OP_ECB_ENC):
-        sel = np.flatnonzero(op == o)
-        assert (np.diff(key[sel]) >= 0).all()
-        for k in np.unique(key[sel]):
-            assert (np.diff(units["offset"][sel][key[sel] == k].astype(np.int64)) > 0).all()
     assert np.flatnonzero(op == ag.AES_OP_CTR).max() < np.flatnonzero(op == ag.AES_OP_ECB_ENC).min()
