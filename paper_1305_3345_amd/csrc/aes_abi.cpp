@@ -11,9 +11,11 @@
 #include <string.h>
 
 #include <algorithm>
+#include <memory>
 #include <new>
 #include <vector>
 
+#include "host_pool.h"
 #include "internal.h"
 
 using namespace aesgpu;
@@ -310,6 +312,7 @@ struct aes_ctx {
     // arrays, and the plan of the batch.
     std::vector<aes_req_t> scratch_reqs;
     Planned scratch_plan;
+    std::unique_ptr<HostPool> pool;  // large single-op calls (created on first use)
 };
 
 struct aes_graph {
@@ -507,6 +510,204 @@ int run_batch(aes_ctx *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
     return AES_OK;
 }
 
+// --------------------------------------------- large single-op calls, in parallel
+
+// Requests per chunk of the parallel single-call path, and the smallest call
+// it takes (below that, thread hand-off costs more than it saves).
+constexpr uint64_t PAR_CHUNK = 4096;
+constexpr uint64_t PAR_MIN_REQS = 2 * PAR_CHUNK;
+constexpr int PAR_MAX_THREADS = 8;
+
+struct ChunkScan {
+    uint64_t err_at = UINT64_MAX;  // first request that breaks a rule
+    int err = AES_OK;
+    bool ordered = true;  // nonzero requests in offset order and disjoint
+    uint64_t first_off = UINT64_MAX, last_end = 0;
+    uint64_t tiles = 0, payload = 0, extent = 0;
+    bool pred_in = false;
+};
+
+// A single-op call over tiles (CBC decryption, CTR, ECB) with many requests:
+// the requests are checked in chunks on the context's threads (same rules and
+// error precedence as validate), then each chunk writes its unit records
+// straight into the pinned staging buffer at offsets from a prefix sum, in
+// request order.  Returns 1 when the call is not for this path.
+int single_parallel(uint32_t op, aes_ctx *ctx, const aes_schedule_t *d_scheds,
+                    uint32_t n_scheds, const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
+                    const uint64_t *offsets, const uint64_t *lengths, const uint32_t *key_idx,
+                    const uint8_t *ivs, uint64_t n, void *stream) {
+    if (n < PAR_MIN_REQS || op == AES_OP_CBC_ENC ||
+        (op == AES_OP_CTR && ctx->ctr_variant == AES_CTR_BITSLICE) ||
+        n / PAR_CHUNK >= (1ull << 30))
+        return 1;
+    int st = check_buffers(d_in, d_out, buf_bytes, n, d_scheds);
+    if (st)
+        return st;
+    if (!ctx->pool) {
+        const unsigned hw = std::thread::hardware_concurrency();
+        const int t = (int)std::min<unsigned>(hw ? hw : 1, PAR_MAX_THREADS);
+        try {
+            ctx->pool.reset(new HostPool(t - 1));
+        } catch (...) {
+            return 1;
+        }
+    }
+    const uint32_t tile = ctx->tile_bytes;
+    const bool dec = is_dec_tile_op(op);
+    const uint64_t n_chunks = (n + PAR_CHUNK - 1) / PAR_CHUNK;
+    std::vector<ChunkScan> sc;
+    std::vector<uint64_t> base;
+    try {
+        sc.resize(n_chunks);
+        base.resize(n_chunks + 1);
+    } catch (const std::bad_alloc &) {
+        return AES_ERR_NOMEM;
+    }
+    // 1. Rules, order and unit counts per chunk.
+    ctx->pool->run((int)n_chunks, [&](int c) {
+        ChunkScan &k = sc[c];
+        const uint64_t lo = (uint64_t)c * PAR_CHUNK, hi = std::min(n, lo + PAR_CHUNK);
+        for (uint64_t i = lo; i < hi; i++) {
+            const uint64_t off = offsets[i], len = lengths[i];
+            int e = AES_OK;
+            if (len > MAX_REQ_BYTES || (op != AES_OP_CTR && (len & 15)))
+                e = AES_ERR_LENGTH;
+            else if ((off & 15) || off > buf_bytes || len > buf_bytes - off ||
+                     key_idx[i] >= n_scheds || key_idx[i] >= MAX_KEYS)
+                e = AES_ERR_RANGE;
+            if (e) {
+                k.err_at = i;
+                k.err = e;
+                return;
+            }
+            if (!len)
+                continue;
+            if (off < k.last_end || (k.first_off != UINT64_MAX && off < k.first_off))
+                k.ordered = false;
+            if (k.first_off == UINT64_MAX)
+                k.first_off = off;
+            k.last_end = std::max(k.last_end, off + len);
+            k.tiles += (len + tile - 1) / tile;
+            k.payload += len;
+            k.extent = std::max(k.extent, off + len);
+            k.pred_in |= dec && op == AES_OP_CBC_DEC && len > tile;
+        }
+    });
+    // 2. The first error in request order, then disjointness.
+    uint64_t err_at = UINT64_MAX, payload = 0;
+    bool ordered = true, pred_in = false;
+    uint64_t prev_end = 0;
+    base[0] = 0;
+    for (uint64_t c = 0; c < n_chunks; c++) {
+        if (sc[c].err_at < err_at) {
+            err_at = sc[c].err_at;
+            st = sc[c].err;
+        }
+        ordered = ordered && sc[c].ordered &&
+                  (sc[c].first_off == UINT64_MAX || sc[c].first_off >= prev_end);
+        if (sc[c].first_off != UINT64_MAX)
+            prev_end = sc[c].last_end;
+        payload += sc[c].payload;
+        pred_in |= sc[c].pred_in;
+        base[c + 1] = base[c] + sc[c].tiles;
+    }
+    if (err_at != UINT64_MAX)
+        return st;
+    if (!ordered) {  // unsorted (or overlapping): the sort-based check
+        std::vector<std::pair<uint64_t, uint64_t>> ranges;
+        try {
+            ranges.reserve(n);
+        } catch (const std::bad_alloc &) {
+            return AES_ERR_NOMEM;
+        }
+        for (uint64_t i = 0; i < n; i++)
+            if (lengths[i])
+                ranges.emplace_back(offsets[i], offsets[i] + lengths[i]);
+        std::sort(ranges.begin(), ranges.end());
+        for (size_t i = 1; i < ranges.size(); i++)
+            if (ranges[i].first < ranges[i - 1].second)
+                return AES_ERR_OVERLAP;
+    }
+    const uint64_t n_tiles = base[n_chunks];
+    if (n_tiles >= (1ull << 32))
+        return AES_ERR_RANGE;
+    if (!payload)
+        return AES_OK;
+    if (ctx->device == AES_DEVICE_NONE)
+        return AES_ERR_DEVICE;
+    HIP_TRY(hipSetDevice(ctx->device));
+    Slot &s = ctx->slots[ctx->next_slot];
+    ctx->next_slot = (ctx->next_slot + 1) % aes_ctx::N_SLOTS;
+    if (s.ev_pending) {
+        HIP_TRY(hipEventSynchronize(s.ev));
+        s.ev_pending = false;
+    }
+    const size_t n_dec = dec ? n_tiles : 0, n_enc = dec ? 0 : n_tiles;
+    const size_t ubytes = n_tiles * sizeof(Unit);
+    const size_t need = units_bytes(n_dec, n_enc, 0);
+    if (s.h_cap < ubytes) {
+        if (s.h_stage)
+            (void)hipHostFree(s.h_stage);
+        s.h_stage = nullptr;
+        s.h_cap = 0;
+        if (hipHostMalloc(&s.h_stage, ubytes, hipHostMallocDefault) != hipSuccess)
+            return AES_ERR_NOMEM;
+        s.h_cap = ubytes;
+    }
+    if (s.d_cap < need) {
+        if (s.d_units)
+            (void)hipFree(s.d_units);
+        s.d_units = nullptr;
+        s.d_cap = 0;
+        if (hipMalloc(&s.d_units, need) != hipSuccess)
+            return AES_ERR_NOMEM;
+        s.d_cap = need;
+    }
+    // 3. Unit records, in request order, into the staging buffer.
+    Unit *out = (Unit *)s.h_stage;
+    ctx->pool->run((int)n_chunks, [&](int c) {
+        const uint64_t lo = (uint64_t)c * PAR_CHUNK, hi = std::min(n, lo + PAR_CHUNK);
+        Unit *u = out + base[c];
+        for (uint64_t i = lo; i < hi; i++) {
+            const uint64_t off = offsets[i], len = lengths[i];
+            if (!len)
+                continue;
+            const uint32_t meta = key_idx[i] | (op << META_OP_SHIFT);
+            const uint8_t *iv = ivs ? ivs + 16 * i : nullptr;
+            const uint64_t ctr0 = op == AES_OP_CTR ? be64(iv + 8) : 0;
+            for (uint64_t pos = 0; pos < len; pos += tile, u++) {
+                u->off = off + pos;
+                u->nbytes = (uint32_t)std::min<uint64_t>(tile, len - pos);
+                u->meta = meta;
+                if (op == AES_OP_CTR) {
+                    const uint64_t ctr = ctr0 + pos / 16;  // mod 2^64, nonce untouched
+                    u->w[0] = le32(iv);
+                    u->w[1] = le32(iv + 4);
+                    u->w[2] = (uint32_t)ctr;
+                    u->w[3] = (uint32_t)(ctr >> 32);
+                } else if (op == AES_OP_CBC_DEC && pos == 0) {
+                    for (int w = 0; w < 4; w++)
+                        u->w[w] = le32(iv + 4 * w);
+                } else {
+                    if (op == AES_OP_CBC_DEC)
+                        u->meta |= FLAG_PRED_IN;
+                    u->w[0] = u->w[1] = u->w[2] = u->w[3] = 0;
+                }
+            }
+        }
+    });
+    HIP_TRY(hipMemcpyAsync(s.d_units, s.h_stage, ubytes, hipMemcpyHostToDevice,
+                           (hipStream_t)stream));
+    PlanView v{s.d_units, n_dec, n_enc, 0, pred_in, dec ? payload : 0, dec ? 0 : payload,
+               op == AES_OP_ECB_ENC ? n_enc : 0};
+    st = launch_planned(ctx, v, d_scheds, n_scheds, d_in, d_out, stream);
+    if (st)
+        return st;
+    HIP_TRY(hipEventRecord(s.ev, (hipStream_t)stream));
+    s.ev_pending = true;
+    return AES_OK;
+}
+
 int single_mode(uint32_t op, aes_ctx *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
                 const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes, const uint64_t *offsets,
                 const uint64_t *lengths, const uint32_t *key_idx, const uint8_t *ivs, uint64_t n,
@@ -516,6 +717,10 @@ int single_mode(uint32_t op, aes_ctx *ctx, const aes_schedule_t *d_scheds, uint3
     const bool ecb = op == AES_OP_ECB_ENC || op == AES_OP_ECB_DEC;  // no IVs
     if (n && (!offsets || !lengths || !key_idx || (!ivs && !ecb)))
         return AES_ERR_ARG;
+    const int pst = single_parallel(op, ctx, d_scheds, n_scheds, d_in, d_out, buf_bytes, offsets,
+                                    lengths, key_idx, ecb ? nullptr : ivs, n, stream);
+    if (pst != 1)
+        return pst;
     std::vector<aes_req_t> &reqs = ctx->scratch_reqs;
     try {
         reqs.resize(n);

@@ -329,3 +329,68 @@ def test_plan_orders_encryption_tiles(ag, hctx, spread, variant):
     plan.close()
     op = (units["meta"] >> 24) & 7
     assert np.flatnonzero(op == ag.AES_OP_CTR).max() < np.flatnonzero(op == ag.AES_OP_ECB_ENC).min()
+
+
+def _status(fn, *a, **k):
+    from paper_1305_3345_amd import aesgpu
+    try:
+        fn(*a, **k)
+    except aesgpu.AesError as e:
+        return e.status
+    return 0
+
+
+@pytest.mark.parametrize("op", ["cbc_dec", "ctr", "ecb_enc", "ecb_dec"])
+def test_large_single_calls_validate_like_plans(ag, hctx, op):
+    """Single-op calls of 20,000 requests take the chunked parallel path
+    (chunks of 4,096); every rule violation, overlap and ordering case --
+    inside a chunk, across a chunk boundary, and two errors at once -- must
+    give the status the serial validator of aes_plan_create gives."""
+    n, page = 20000, 4096
+    opnum = {"cbc_dec": ag.AES_OP_CBC_DEC, "ctr": ag.AES_OP_CTR, "ecb_enc": ag.AES_OP_ECB_ENC,
+             "ecb_dec": ag.AES_OP_ECB_DEC}[op]
+    fn = {"cbc_dec": ag.cbc_decrypt_batch, "ctr": ag.ctr_batch, "ecb_enc": ag.ecb_encrypt_batch,
+          "ecb_dec": ag.ecb_decrypt_batch}[op]
+    buf = n * page
+
+    def base():
+        r = np.zeros(n, workloads.REQ_DTYPE)
+        r["offset"] = np.arange(n, dtype=np.uint64) * page
+        r["length"] = page
+        r["op"] = opnum
+        r["key_idx"] = np.arange(n) % 16
+        r["iv"] = gen.bytes_(7, 2, 16 * n).reshape(n, 16)
+        r["length"][::97] = 0
+        return r
+
+    cases = {"valid": lambda r: None}
+    for k in (3, 4095, 4096, 12000, n - 1):
+        cases[f"misaligned@{k}"] = lambda r, k=k: r["offset"].__setitem__(k, r["offset"][k] + 8)
+        cases[f"past_end@{k}"] = lambda r, k=k: r["length"].__setitem__(k, buf)
+        cases[f"bad_key@{k}"] = lambda r, k=k: r["key_idx"].__setitem__(k, 16)
+        cases[f"overlap@{k}"] = lambda r, k=k: r["length"].__setitem__(k - 1, 2 * page)
+        cases[f"ragged@{k}"] = lambda r, k=k: r["length"].__setitem__(k, page - 8)
+    cases["permuted"] = lambda r: r.__setitem__(slice(None), r[np.random.default_rng(1).permutation(n)])
+
+    def permuted_overlap(r):
+        r["length"][5000] = 2 * page
+        r[:] = r[np.random.default_rng(2).permutation(n)]
+    cases["permuted_overlap"] = permuted_overlap
+
+    def two_errors_a(r):  # range error before a length error
+        r["key_idx"][9000] = 99
+        r["length"][15000] = page - 8
+
+    def two_errors_b(r):  # overlap early, range error late: rules come first
+        r["length"][100] = 2 * page
+        r["offset"][19000] += 8
+    cases["two_errors_a"] = two_errors_a
+    cases["two_errors_b"] = two_errors_b
+    for name, mutate in cases.items():
+        r = base()
+        mutate(r)
+        want = _status(ag.Plan, hctx, r, 16, buf)
+        want = ag.AES_ERR_DEVICE if want == 0 else want  # a plan is made; a call needs the GPU
+        got = _status(fn, hctx, FAKE, FAKE, FAKE + (1 << 40), r["offset"], r["length"],
+                      r["key_idx"], r["iv"], buf_bytes=buf, n_scheds=16)
+        assert got == want, f"{op} {name}: call {got}, plan {want}"
