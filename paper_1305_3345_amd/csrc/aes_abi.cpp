@@ -289,6 +289,7 @@ struct Slot {
     size_t d_cap = 0;
     hipEvent_t ev = nullptr;  // recorded after the last launch that used the slot
     bool ev_pending = false;
+    hipEvent_t copied = nullptr;  // the unit table's upload on the copy stream
 };
 
 struct aes_ctx {
@@ -313,6 +314,7 @@ struct aes_ctx {
     std::vector<aes_req_t> scratch_reqs;
     Planned scratch_plan;
     std::unique_ptr<HostPool> pool;  // large single-op calls (created on first use)
+    hipStream_t copy = nullptr;      // unit-table uploads of the single-call forms
 };
 
 struct aes_graph {
@@ -358,6 +360,28 @@ struct PlanView {
 PlanView view_of(const Planned &p, void *d_units) {
     return PlanView{d_units, p.dec.size(), p.ctr.size(), p.chains.size(), p.dec_has_pred_in,
                     p.dec_bytes, p.ctr_bytes, p.n_ecb};
+}
+
+// Uploads a slot's unit table for a launch on `stream`.  When the stream is
+// not being captured, the copy goes on the context's copy stream and the
+// launch waits for it by event, so the upload of one call overlaps the
+// kernels of the call before; under capture it stays on `stream`.  The slot
+// is free of earlier uploads and launches (its event was waited for).
+int upload_units(aes_ctx *ctx, Slot &s, size_t ubytes, void *stream) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing((hipStream_t)stream, &cap));
+    if (cap == hipStreamCaptureStatusNone && !ctx->copy &&
+        hipStreamCreateWithFlags(&ctx->copy, hipStreamNonBlocking) != hipSuccess)
+        ctx->copy = nullptr;
+    if (cap != hipStreamCaptureStatusNone || !ctx->copy) {
+        HIP_TRY(hipMemcpyAsync(s.d_units, s.h_stage, ubytes, hipMemcpyHostToDevice,
+                               (hipStream_t)stream));
+        return AES_OK;
+    }
+    HIP_TRY(hipMemcpyAsync(s.d_units, s.h_stage, ubytes, hipMemcpyHostToDevice, ctx->copy));
+    HIP_TRY(hipEventRecord(s.copied, ctx->copy));
+    HIP_TRY(hipStreamWaitEvent((hipStream_t)stream, s.copied, 0));
+    return AES_OK;
 }
 
 // Workgroups of the fused kernel that hold the decryption tables: a share of
@@ -500,8 +524,8 @@ int run_batch(aes_ctx *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
         s.d_cap = need;
     }
     pack_units(p, s.h_stage);
-    HIP_TRY(hipMemcpyAsync(s.d_units, s.h_stage, ubytes, hipMemcpyHostToDevice,
-                           (hipStream_t)stream));
+    if ((st = upload_units(ctx, s, ubytes, stream)))
+        return st;
     st = launch_planned(ctx, view_of(p, s.d_units), d_scheds, n_scheds, d_in, d_out, stream);
     if (st)
         return st;
@@ -696,8 +720,8 @@ int single_parallel(uint32_t op, aes_ctx *ctx, const aes_schedule_t *d_scheds,
             }
         }
     });
-    HIP_TRY(hipMemcpyAsync(s.d_units, s.h_stage, ubytes, hipMemcpyHostToDevice,
-                           (hipStream_t)stream));
+    if ((st = upload_units(ctx, s, ubytes, stream)))
+        return st;
     PlanView v{s.d_units, n_dec, n_enc, 0, pred_in, dec ? payload : 0, dec ? 0 : payload,
                op == AES_OP_ECB_ENC ? n_enc : 0};
     st = launch_planned(ctx, v, d_scheds, n_scheds, d_in, d_out, stream);
@@ -805,7 +829,8 @@ int aes_ctx_create(int hip_device, aes_ctx_t **out) {
             return hip_fail(e);
         }
         for (Slot &s : ctx->slots) {
-            if ((e = hipEventCreateWithFlags(&s.ev, hipEventDisableTiming)) != hipSuccess) {
+            if ((e = hipEventCreateWithFlags(&s.ev, hipEventDisableTiming)) != hipSuccess ||
+                (e = hipEventCreateWithFlags(&s.copied, hipEventDisableTiming)) != hipSuccess) {
                 aes_ctx_destroy(ctx);
                 return hip_fail(e);
             }
@@ -826,6 +851,8 @@ void aes_ctx_destroy(aes_ctx_t *ctx) {
                     (void)hipEventSynchronize(s.ev);
                 (void)hipEventDestroy(s.ev);
             }
+            if (s.copied)
+                (void)hipEventDestroy(s.copied);
             if (s.h_stage)
                 (void)hipHostFree(s.h_stage);
             if (s.d_units)
@@ -835,6 +862,10 @@ void aes_ctx_destroy(aes_ctx_t *ctx) {
             (void)hipFree(ctx->d_timg);
         if (ctx->capture)
             (void)hipStreamDestroy(ctx->capture);
+        if (ctx->copy) {
+            (void)hipStreamSynchronize(ctx->copy);
+            (void)hipStreamDestroy(ctx->copy);
+        }
     }
     delete ctx;
 }
