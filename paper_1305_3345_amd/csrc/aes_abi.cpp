@@ -47,6 +47,18 @@ constexpr uint32_t DEFAULT_TILE = 4096;
 
 // ------------------------------------------------------------- validation
 
+// The rules one request must meet (op already known to be valid), in the
+// order whose first failure a call reports.
+inline int check_request(uint32_t op, uint64_t off, uint64_t len, uint32_t key,
+                         uint32_t n_scheds, uint64_t buf_bytes) {
+    if (len > MAX_REQ_BYTES || (op != AES_OP_CTR && (len & 15)))
+        return AES_ERR_LENGTH;
+    if ((off & 15) || off > buf_bytes || len > buf_bytes - off || key >= n_scheds ||
+        key >= MAX_KEYS)
+        return AES_ERR_RANGE;
+    return AES_OK;
+}
+
 // Checks one request list against buffer size and schedule count, and that
 // the written byte ranges are pairwise disjoint.
 int validate(const aes_req_t *reqs, uint64_t n, uint32_t n_scheds, uint64_t buf_bytes) {
@@ -58,14 +70,9 @@ int validate(const aes_req_t *reqs, uint64_t n, uint32_t n_scheds, uint64_t buf_
         const aes_req_t &r = reqs[i];
         if (r.op > AES_OP_ECB_DEC)
             return AES_ERR_ARG;
-        if (r.length > MAX_REQ_BYTES)
-            return AES_ERR_LENGTH;
-        if (r.op != AES_OP_CTR && (r.length & 15))
-            return AES_ERR_LENGTH;
-        if ((r.offset & 15) || r.offset > buf_bytes || r.length > buf_bytes - r.offset)
-            return AES_ERR_RANGE;
-        if (r.key_idx >= n_scheds || r.key_idx >= MAX_KEYS)
-            return AES_ERR_RANGE;
+        const int st = check_request(r.op, r.offset, r.length, r.key_idx, n_scheds, buf_bytes);
+        if (st)
+            return st;
         if (r.length) {
             if (r.offset < last_off)
                 sorted = false;
@@ -362,6 +369,39 @@ PlanView view_of(const Planned &p, void *d_units) {
                     p.dec_bytes, p.ctr_bytes, p.n_ecb};
 }
 
+// Takes the context's next staging slot for a call whose unit table has
+// ubytes bytes (need = device bytes with the in-place snapshots): waits for
+// the slot's last launch, then grows its pinned and device buffers if needed.
+int take_slot(aes_ctx *ctx, size_t ubytes, size_t need, Slot **out) {
+    HIP_TRY(hipSetDevice(ctx->device));
+    Slot &s = ctx->slots[ctx->next_slot];
+    ctx->next_slot = (ctx->next_slot + 1) % aes_ctx::N_SLOTS;
+    if (s.ev_pending) {
+        HIP_TRY(hipEventSynchronize(s.ev));
+        s.ev_pending = false;
+    }
+    if (s.h_cap < ubytes) {
+        if (s.h_stage)
+            (void)hipHostFree(s.h_stage);
+        s.h_stage = nullptr;
+        s.h_cap = 0;
+        if (hipHostMalloc(&s.h_stage, ubytes, hipHostMallocDefault) != hipSuccess)
+            return AES_ERR_NOMEM;
+        s.h_cap = ubytes;
+    }
+    if (s.d_cap < need) {
+        if (s.d_units)
+            (void)hipFree(s.d_units);
+        s.d_units = nullptr;
+        s.d_cap = 0;
+        if (hipMalloc(&s.d_units, need) != hipSuccess)
+            return AES_ERR_NOMEM;
+        s.d_cap = need;
+    }
+    *out = &s;
+    return AES_OK;
+}
+
 // Uploads a slot's unit table for a launch on `stream`.  When the stream is
 // not being captured, the copy goes on the context's copy stream and the
 // launch waits for it by event, so the upload of one call overlaps the
@@ -496,33 +536,12 @@ int run_batch(aes_ctx *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
         return AES_OK;
     if (ctx->device == AES_DEVICE_NONE)
         return AES_ERR_DEVICE;
-    HIP_TRY(hipSetDevice(ctx->device));
-    Slot &s = ctx->slots[ctx->next_slot];
-    ctx->next_slot = (ctx->next_slot + 1) % aes_ctx::N_SLOTS;
-    if (s.ev_pending) {
-        HIP_TRY(hipEventSynchronize(s.ev));
-        s.ev_pending = false;
-    }
     const size_t ubytes = (p.dec.size() + p.ctr.size() + p.chains.size()) * sizeof(Unit);
     const size_t need = units_bytes(p.dec.size(), p.ctr.size(), p.chains.size());
-    if (s.h_cap < ubytes) {
-        if (s.h_stage)
-            (void)hipHostFree(s.h_stage);
-        s.h_stage = nullptr;
-        s.h_cap = 0;
-        if (hipHostMalloc(&s.h_stage, ubytes, hipHostMallocDefault) != hipSuccess)
-            return AES_ERR_NOMEM;
-        s.h_cap = ubytes;
-    }
-    if (s.d_cap < need) {
-        if (s.d_units)
-            (void)hipFree(s.d_units);
-        s.d_units = nullptr;
-        s.d_cap = 0;
-        if (hipMalloc(&s.d_units, need) != hipSuccess)
-            return AES_ERR_NOMEM;
-        s.d_cap = need;
-    }
+    Slot *sp = nullptr;
+    if ((st = take_slot(ctx, ubytes, need, &sp)))
+        return st;
+    Slot &s = *sp;
     pack_units(p, s.h_stage);
     if ((st = upload_units(ctx, s, ubytes, stream)))
         return st;
@@ -593,12 +612,7 @@ int single_parallel(uint32_t op, aes_ctx *ctx, const aes_schedule_t *d_scheds,
         const uint64_t lo = (uint64_t)c * PAR_CHUNK, hi = std::min(n, lo + PAR_CHUNK);
         for (uint64_t i = lo; i < hi; i++) {
             const uint64_t off = offsets[i], len = lengths[i];
-            int e = AES_OK;
-            if (len > MAX_REQ_BYTES || (op != AES_OP_CTR && (len & 15)))
-                e = AES_ERR_LENGTH;
-            else if ((off & 15) || off > buf_bytes || len > buf_bytes - off ||
-                     key_idx[i] >= n_scheds || key_idx[i] >= MAX_KEYS)
-                e = AES_ERR_RANGE;
+            const int e = check_request(op, off, len, key_idx[i], n_scheds, buf_bytes);
             if (e) {
                 k.err_at = i;
                 k.err = e;
@@ -659,34 +673,13 @@ int single_parallel(uint32_t op, aes_ctx *ctx, const aes_schedule_t *d_scheds,
         return AES_OK;
     if (ctx->device == AES_DEVICE_NONE)
         return AES_ERR_DEVICE;
-    HIP_TRY(hipSetDevice(ctx->device));
-    Slot &s = ctx->slots[ctx->next_slot];
-    ctx->next_slot = (ctx->next_slot + 1) % aes_ctx::N_SLOTS;
-    if (s.ev_pending) {
-        HIP_TRY(hipEventSynchronize(s.ev));
-        s.ev_pending = false;
-    }
     const size_t n_dec = dec ? n_tiles : 0, n_enc = dec ? 0 : n_tiles;
     const size_t ubytes = n_tiles * sizeof(Unit);
     const size_t need = units_bytes(n_dec, n_enc, 0);
-    if (s.h_cap < ubytes) {
-        if (s.h_stage)
-            (void)hipHostFree(s.h_stage);
-        s.h_stage = nullptr;
-        s.h_cap = 0;
-        if (hipHostMalloc(&s.h_stage, ubytes, hipHostMallocDefault) != hipSuccess)
-            return AES_ERR_NOMEM;
-        s.h_cap = ubytes;
-    }
-    if (s.d_cap < need) {
-        if (s.d_units)
-            (void)hipFree(s.d_units);
-        s.d_units = nullptr;
-        s.d_cap = 0;
-        if (hipMalloc(&s.d_units, need) != hipSuccess)
-            return AES_ERR_NOMEM;
-        s.d_cap = need;
-    }
+    Slot *sp = nullptr;
+    if ((st = take_slot(ctx, ubytes, need, &sp)))
+        return st;
+    Slot &s = *sp;
     // 3. Unit records, in request order, into the staging buffer.
     Unit *out = (Unit *)s.h_stage;
     ctx->pool->run((int)n_chunks, [&](int c) {
