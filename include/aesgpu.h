@@ -216,8 +216,10 @@ typedef struct aes_plan_info {
 int aes_plan_create(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_scheds,
                     uint64_t buf_bytes, aes_plan_t **out);
 /* Launches a plan on stream over buffers of the plan's buf_bytes.  d_in may
- * equal d_out (in-place).  Errors: AES_ERR_ARG, AES_ERR_OVERLAP,
- * AES_ERR_DEVICE. */
+ * equal d_out (in-place).  Launches of one plan (or replays of a graph made
+ * from it) must not overlap in time: the tile kernels' work counters live in
+ * the plan, so issue them on one stream or order them with events.  Errors:
+ * AES_ERR_ARG, AES_ERR_OVERLAP, AES_ERR_DEVICE. */
 int aes_plan_launch(aes_plan_t *plan, const aes_schedule_t *d_scheds, const uint8_t *d_in,
                     uint8_t *d_out, void *stream);
 int aes_plan_info(const aes_plan_t *plan, aes_plan_info_t *info);
@@ -302,7 +304,8 @@ int aes_request_launches(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_
 /* An instantiated HIP graph owned by the library. */
 typedef struct aes_graph aes_graph_t;
 
-/* Captures one launch of a plan (with these buffers) into a graph. */
+/* Captures one launch of a plan (with these buffers) into a graph; its
+ * replays count as launches of the plan (they must not overlap them). */
 int aes_plan_graph(aes_plan_t *plan, const aes_schedule_t *d_scheds, const uint8_t *d_in,
                    uint8_t *d_out, aes_graph_t **out);
 /* Captures n_reqs per-request launches (aes_request_launch) into one graph. */

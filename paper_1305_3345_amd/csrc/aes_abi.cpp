@@ -297,6 +297,7 @@ struct Slot {
     hipEvent_t ev = nullptr;  // recorded after the last launch that used the slot
     bool ev_pending = false;
     hipEvent_t copied = nullptr;  // the unit table's upload on the copy stream
+    uint32_t *d_ctrs = nullptr;   // tile-kernel counters: decryption side, then encryption
 };
 
 struct aes_ctx {
@@ -337,6 +338,7 @@ struct aes_plan {
     uint32_t n_scheds = 0;
     uint64_t buf_bytes = 0;
     void *d_units = nullptr;  // [dec | ctr | chains] units, then dec predecessor snapshots
+    uint32_t *d_ctrs = nullptr;  // tile-kernel counters: decryption side, then encryption
     size_t n_dec = 0, n_ctr = 0, n_chain = 0;
     uint32_t tile_bytes = DEFAULT_TILE;
 };
@@ -358,15 +360,33 @@ size_t units_bytes(size_t n_dec, size_t n_ctr, size_t n_chain) {
 
 struct PlanView {
     void *d_units;
+    uint32_t *d_ctrs;  // 2 x TILE_CTRS zeroed counters of the tile launches
     size_t n_dec, n_ctr, n_chain;
     bool pred_in;
     uint64_t dec_bytes, ctr_bytes;
     size_t n_ecb;  // ECB-encrypt tiles: the last n_ecb of the n_ctr encryption tiles
 };
 
-PlanView view_of(const Planned &p, void *d_units) {
-    return PlanView{d_units, p.dec.size(), p.ctr.size(), p.chains.size(), p.dec_has_pred_in,
+PlanView view_of(const Planned &p, void *d_units, uint32_t *d_ctrs) {
+    return PlanView{d_units, d_ctrs, p.dec.size(), p.ctr.size(), p.chains.size(), p.dec_has_pred_in,
                     p.dec_bytes, p.ctr_bytes, p.n_ecb};
+}
+
+// Zeroed tile-kernel counters for one plan or staging slot (the kernels
+// leave them zeroed after every launch).
+int alloc_tile_ctrs(uint32_t **out) {
+    const size_t bytes = 2 * (size_t)TILE_CTRS * sizeof(uint32_t);
+    if (hipMalloc((void **)out, bytes) != hipSuccess) {
+        *out = nullptr;
+        return AES_ERR_NOMEM;
+    }
+    const hipError_t e = hipMemset(*out, 0, bytes);
+    if (e != hipSuccess) {
+        (void)hipFree(*out);
+        *out = nullptr;
+        return hip_fail(e);
+    }
+    return AES_OK;
 }
 
 // Takes the context's next staging slot for a call whose unit table has
@@ -397,6 +417,11 @@ int take_slot(aes_ctx *ctx, size_t ubytes, size_t need, Slot **out) {
         if (hipMalloc(&s.d_units, need) != hipSuccess)
             return AES_ERR_NOMEM;
         s.d_cap = need;
+    }
+    if (!s.d_ctrs) {
+        const int st = alloc_tile_ctrs(&s.d_ctrs);
+        if (st)
+            return st;
     }
     *out = &s;
     return AES_OK;
@@ -496,10 +521,11 @@ int launch_planned(aes_ctx *ctx, const PlanView &v, const aes_schedule_t *d_sche
         return AES_OK;
     }
     if ((e = launch_cbcdec_tiles(u_dec, (uint32_t)v.n_dec, d_scheds, n_scheds, ctx->d_timg,
-                                 d_preds, d_in, d_out, ctx->tile_dec, ctx->n_cu, stream)))
+                                 d_preds, d_in, d_out, v.d_ctrs, ctx->tile_dec, ctx->n_cu,
+                                 stream)))
         return hip_fail((hipError_t)e);
     if ((e = launch_ctr_tiles(u_ctr, (uint32_t)n_ctr_tab, d_scheds, n_scheds, ctx->d_timg, d_in,
-                              d_out, ctx->tile_ctr, ctx->n_cu, stream)))
+                              d_out, v.d_ctrs + TILE_CTRS, ctx->tile_ctr, ctx->n_cu, stream)))
         return hip_fail((hipError_t)e);
     if ((e = launch_cbcenc_chains(u_chain, (uint32_t)v.n_chain, d_scheds, n_scheds, ctx->d_timg,
                                   d_in, d_out, ctx->chain, ctx->n_cu, stream)))
@@ -545,7 +571,8 @@ int run_batch(aes_ctx *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
     pack_units(p, s.h_stage);
     if ((st = upload_units(ctx, s, ubytes, stream)))
         return st;
-    st = launch_planned(ctx, view_of(p, s.d_units), d_scheds, n_scheds, d_in, d_out, stream);
+    st = launch_planned(ctx, view_of(p, s.d_units, s.d_ctrs), d_scheds, n_scheds, d_in, d_out,
+                        stream);
     if (st)
         return st;
     HIP_TRY(hipEventRecord(s.ev, (hipStream_t)stream));
@@ -715,7 +742,7 @@ int single_parallel(uint32_t op, aes_ctx *ctx, const aes_schedule_t *d_scheds,
     });
     if ((st = upload_units(ctx, s, ubytes, stream)))
         return st;
-    PlanView v{s.d_units, n_dec, n_enc, 0, pred_in, dec ? payload : 0, dec ? 0 : payload,
+    PlanView v{s.d_units, s.d_ctrs, n_dec, n_enc, 0, pred_in, dec ? payload : 0, dec ? 0 : payload,
                op == AES_OP_ECB_ENC ? n_enc : 0};
     st = launch_planned(ctx, v, d_scheds, n_scheds, d_in, d_out, stream);
     if (st)
@@ -850,6 +877,8 @@ void aes_ctx_destroy(aes_ctx_t *ctx) {
                 (void)hipHostFree(s.h_stage);
             if (s.d_units)
                 (void)hipFree(s.d_units);
+            if (s.d_ctrs)
+                (void)hipFree(s.d_ctrs);
         }
         if (ctx->d_timg)
             (void)hipFree(ctx->d_timg);
@@ -962,6 +991,11 @@ int aes_plan_create(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n, uint32_t 
             delete pl;
             return hip_fail(e);
         }
+        if ((st = alloc_tile_ctrs(&pl->d_ctrs))) {
+            (void)hipFree(pl->d_units);
+            delete pl;
+            return st;
+        }
     }
     *out = pl;
     return AES_OK;
@@ -981,7 +1015,7 @@ int aes_plan_launch(aes_plan_t *plan, const aes_schedule_t *d_scheds, const uint
     if (ctx->device == AES_DEVICE_NONE)
         return AES_ERR_DEVICE;
     HIP_TRY(hipSetDevice(ctx->device));
-    return launch_planned(ctx, view_of(plan->p, plan->d_units), d_scheds, plan->n_scheds, d_in,
+    return launch_planned(ctx, view_of(plan->p, plan->d_units, plan->d_ctrs), d_scheds, plan->n_scheds, d_in,
                           d_out, stream);
 }
 
@@ -1017,10 +1051,13 @@ int aes_plan_units(const aes_plan_t *plan, aes_unit_t *out, uint64_t max, uint64
 void aes_plan_destroy(aes_plan_t *plan) {
     if (!plan)
         return;
-    if (plan->d_units) {
+    if (plan->d_units || plan->d_ctrs) {
         (void)hipSetDevice(plan->ctx->device);
         (void)hipDeviceSynchronize();
-        (void)hipFree(plan->d_units);
+        if (plan->d_units)
+            (void)hipFree(plan->d_units);
+        if (plan->d_ctrs)
+            (void)hipFree(plan->d_ctrs);
     }
     delete plan;
 }
@@ -1183,7 +1220,7 @@ int aes_plan_graph(aes_plan_t *plan, const aes_schedule_t *d_scheds, const uint8
     if ((st = capture_stream(ctx)))
         return st;
     HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
-    st = plan->p.payload ? launch_planned(ctx, view_of(plan->p, plan->d_units), d_scheds,
+    st = plan->p.payload ? launch_planned(ctx, view_of(plan->p, plan->d_units, plan->d_ctrs), d_scheds,
                                           plan->n_scheds, d_in, d_out, ctx->capture)
                          : AES_OK;
     return finish_capture(ctx, st, 1, out);
@@ -1252,7 +1289,7 @@ int time_plan(aes_plan *plan, const aes_schedule_t *d_scheds, const uint8_t *d_i
     for (int i = 0; i <= iters && !st; i++) {
         hipError_t e = hipEventRecord(a, ctx->capture);
         if (e == hipSuccess) {
-            st = launch_planned(ctx, view_of(plan->p, plan->d_units), d_scheds, plan->n_scheds,
+            st = launch_planned(ctx, view_of(plan->p, plan->d_units, plan->d_ctrs), d_scheds, plan->n_scheds,
                                 d_in, d_out, ctx->capture);
             if (!st)
                 e = hipEventRecord(b, ctx->capture);

@@ -13,9 +13,10 @@ bool tile_shape_supported(int nb, int wg) {
 
 int launch_ctr_tiles(const Unit *d_units, uint32_t n_units, const aes_schedule_t *d_sched,
                      uint32_t n_sched, const uint32_t *d_timg, const uint8_t *d_in,
-                     uint8_t *d_out, const TileLaunch &cfg, int n_cu, void *stream) {
+                     uint8_t *d_out, uint32_t *d_ctrs, const TileLaunch &cfg, int n_cu,
+                     void *stream) {
     return launch_tiles<false>(d_units, n_units, d_sched, n_sched, d_timg, nullptr, d_in, d_out,
-                               cfg, n_cu, stream);
+                               d_ctrs, cfg, n_cu, stream);
 }
 
 }  // namespace aesgpu

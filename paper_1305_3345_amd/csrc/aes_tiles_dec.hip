@@ -10,10 +10,10 @@ namespace aesgpu {
 
 int launch_cbcdec_tiles(const Unit *d_units, uint32_t n_units, const aes_schedule_t *d_sched,
                         uint32_t n_sched, const uint32_t *d_timg, const void *d_preds,
-                        const uint8_t *d_in, uint8_t *d_out, const TileLaunch &cfg, int n_cu,
-                        void *stream) {
+                        const uint8_t *d_in, uint8_t *d_out, uint32_t *d_ctrs,
+                        const TileLaunch &cfg, int n_cu, void *stream) {
     return launch_tiles<true>(d_units, n_units, d_sched, n_sched, d_timg, d_preds, d_in, d_out,
-                              cfg, n_cu, stream);
+                              d_ctrs, cfg, n_cu, stream);
 }
 
 }  // namespace aesgpu

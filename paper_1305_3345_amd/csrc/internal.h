@@ -71,9 +71,13 @@ struct MixedArgs {
 
 // Host-side launchers.  Each returns a hipError_t value.  Tile kernels:
 // aes_tiles_ctr.hip and aes_tiles_dec.hip; the others: aes_kernels.hip.
+// Tile launchers take d_ctrs: TILE_CTRS zeroed per-workgroup counters that
+// every launch leaves zeroed (launches sharing them must not overlap).
+constexpr uint32_t TILE_CTRS = 65536;
 int launch_ctr_tiles(const Unit *d_units, uint32_t n_units, const aes_schedule_t *d_sched,
                      uint32_t n_sched, const uint32_t *d_timg, const uint8_t *d_in,
-                     uint8_t *d_out, const TileLaunch &cfg, int n_cu, void *stream);
+                     uint8_t *d_out, uint32_t *d_ctrs, const TileLaunch &cfg, int n_cu,
+                     void *stream);
 // Bitsliced CTR (aes_bitslice.hip): units in groups of 8 per wave, worked in
 // 4 KiB chunks; a group whose units share a key makes one pass per chunk.
 int launch_ctr_bitslice(const Unit *d_units, uint32_t n_units, const aes_schedule_t *d_sched,
@@ -83,8 +87,8 @@ int launch_ctr_bitslice(const Unit *d_units, uint32_t n_units, const aes_schedul
 // launch_snapshot_preds (used for FLAG_PRED_IN units instead of reading d_in).
 int launch_cbcdec_tiles(const Unit *d_units, uint32_t n_units, const aes_schedule_t *d_sched,
                         uint32_t n_sched, const uint32_t *d_timg, const void *d_preds,
-                        const uint8_t *d_in, uint8_t *d_out, const TileLaunch &cfg, int n_cu,
-                        void *stream);
+                        const uint8_t *d_in, uint8_t *d_out, uint32_t *d_ctrs,
+                        const TileLaunch &cfg, int n_cu, void *stream);
 int launch_cbcenc_chains(const Unit *d_units, uint32_t n_units, const aes_schedule_t *d_sched,
                          uint32_t n_sched, const uint32_t *d_timg, const uint8_t *d_in,
                          uint8_t *d_out, const ChainLaunch &cfg, int n_cu, void *stream);

@@ -11,14 +11,27 @@
 
 namespace aesgpu {
 
-// One table set in LDS per workgroup; wave w works units w, w + W, ... (W
-// waves in the grid).
+// Tile counters: one per workgroup of a tile launch, for each side.
+static_assert(TILE_CTRS == 65536, "one counter per workgroup of the largest grid");
+constexpr uint32_t TILE_MAX_GRID = TILE_CTRS;
+
+// One table set in LDS per workgroup.  Workgroup g owns a contiguous range
+// of units; its waves claim them one at a time from the workgroup's counter
+// in wg_ctr.  The SIMD arbiter runs the oldest wave first, so with a fixed
+// share per wave the first waves of each SIMD finished in about half the time
+// of the last and the CUs ran the final third of a launch with one or two
+// waves per SIMD; with claims, favoured waves simply take more units.  Each
+// claim is made one unit ahead, so its latency overlaps the unit before.
+// Every wave ends on exactly one failing claim; the wave whose failing claim
+// is the last (value range + waves - 1) resets the counter, which is zero
+// again when the launch ends, ready for the next launch of the same plan on
+// the same stream (or a replay of a graph holding it).
 template <bool DEC, int NB, int WG>
 __global__ __launch_bounds__(WG) void k_tiles(const Unit *__restrict__ units, uint32_t n_units,
                                               const aes_schedule_t *__restrict__ sched,
                                               uint32_t n_sched, const uint32_t *__restrict__ timg,
                                               const uint4 *__restrict__ preds, const uint8_t *in,
-                                              uint8_t *out) {
+                                              uint8_t *out, uint32_t *__restrict__ wg_ctr) {
     __shared__ uint32_t lds[DEC ? LDS_DEC_WORDS : LDS_ENC_WORDS];
     fill_tables<DEC>(lds, timg);
     __syncthreads();
@@ -26,23 +39,33 @@ __global__ __launch_bounds__(WG) void k_tiles(const Unit *__restrict__ units, ui
     const uint32_t L0 = (lane & 31u) << 2;
     const uint32_t L2 = L0 | SI_BASE;
     // Waves per workgroup from the template (the kernel is launched with WG
-    // threads), and the wave index and stride made explicitly uniform: the
-    // unit loop, its record and key-schedule loads stay scalar.
+    // threads); the claimed index is made explicitly uniform, so the unit
+    // record and key-schedule loads stay scalar.
     constexpr uint32_t wpb = WG / 64;
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
-    const uint32_t nw = __builtin_amdgcn_readfirstlane(gridDim.x * wpb);
-    for (uint32_t u = wave; u < n_units; u += nw) {
+    const uint32_t g = blockIdx.x;
+    const uint32_t lo = (uint32_t)((uint64_t)n_units * g / gridDim.x);
+    const uint32_t range = (uint32_t)((uint64_t)n_units * (g + 1) / gridDim.x) - lo;
+    uint32_t *cnt = wg_ctr + g;
+    uint32_t got = lane == 0 ? atomicAdd(cnt, 1u) : 0u;
+    uint32_t c = __builtin_amdgcn_readfirstlane(got);
+    while (c < range) {
+        got = lane == 0 ? atomicAdd(cnt, 1u) : 0u;  // the next claim, in flight meanwhile
+        const uint32_t u = lo + c;
         const Unit un = units[u];
         if (DEC)
             run_dec_unit<NB, TILE_NV_DEC>(lds, L0, L2, lane, un, preds ? preds + u : nullptr,
                                           sched, n_sched, in, out);
         else
             run_ctr_unit<NB, TILE_NV_CTR>(lds, L0, lane, un, sched, n_sched, in, out);
+        c = __builtin_amdgcn_readfirstlane(got);
     }
+    if (c == range + wpb - 1 && lane == 0)
+        __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 using TileKernel = void (*)(const Unit *, uint32_t, const aes_schedule_t *, uint32_t,
-                            const uint32_t *, const uint4 *, const uint8_t *, uint8_t *);
+                            const uint32_t *, const uint4 *, const uint8_t *, uint8_t *,
+                            uint32_t *);
 
 // Compiled shapes: blocks per lane NB in {1, 2, 4} x workgroup size WG in
 // {256, 512, 1024}.  The launch bound sets the VGPR budget (WG 1024 gives
@@ -59,11 +82,12 @@ inline TileKernel pick_tile_kernel(int nb, int wg) {
     return nullptr;
 }
 
+// d_ctrs: TILE_MAX_GRID zeroed counters (zero again after every launch).
 template <bool DEC>
 inline int launch_tiles(const Unit *d_units, uint32_t n_units, const aes_schedule_t *d_sched,
                         uint32_t n_sched, const uint32_t *d_timg, const void *d_preds,
-                        const uint8_t *d_in, uint8_t *d_out, const TileLaunch &cfg, int n_cu,
-                        void *stream) {
+                        const uint8_t *d_in, uint8_t *d_out, uint32_t *d_ctrs,
+                        const TileLaunch &cfg, int n_cu, void *stream) {
     if (!n_units)
         return hipSuccess;
     const TileKernel k = pick_tile_kernel<DEC>(cfg.nb, cfg.wg_threads);
@@ -76,8 +100,11 @@ inline int launch_tiles(const Unit *d_units, uint32_t n_units, const aes_schedul
         grid = (int)need;
     if (grid < 1)
         grid = 1;
+    if (!d_ctrs || (uint32_t)grid > TILE_MAX_GRID)
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(k, dim3(grid), dim3(cfg.wg_threads), 0, (hipStream_t)stream, d_units,
-                       n_units, d_sched, n_sched, d_timg, (const uint4 *)d_preds, d_in, d_out);
+                       n_units, d_sched, n_sched, d_timg, (const uint4 *)d_preds, d_in, d_out,
+                       d_ctrs);
     return hipGetLastError();
 }
 
