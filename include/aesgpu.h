@@ -279,8 +279,12 @@ int aes_ctx_set_config(aes_ctx_t *ctx, const aes_launch_config_t *cfg);
  * sizes, tile-kernel shapes, the fused kernel's blocks per lane, chain lanes
  * or four-lane chains, the fusion switch and (for batches with CTR requests)
  * the CTR variant by coordinate descent (median of iters launches each),
- * leaves the fastest configuration set in ctx and copies it to *best (may be
- * NULL).  Plans created afterwards use its tile size.  Errors: as aes_batch; AES_ERR_OVERLAP if d_in == d_out. */
+ * starting from ctx's current configuration; a candidate replaces the best
+ * so far only when it is more than 2% faster, so knobs that do not change
+ * the batch's time keep their starting values.  Leaves the chosen
+ * configuration set in ctx and copies it to *best (may be NULL).  Plans
+ * created afterwards use its tile size.  Errors: as aes_batch;
+ * AES_ERR_OVERLAP if d_in == d_out. */
 int aes_tune(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_scheds,
              uint64_t buf_bytes, const aes_schedule_t *d_scheds, const uint8_t *d_in,
              uint8_t *d_out, uint32_t iters, aes_launch_config_t *best);
