@@ -214,27 +214,31 @@ __device__ __forceinline__ void store_block(uint8_t *dst, uint32_t b, uint32_t n
 // round key scalar, keys plus the loop state exceed the scalar registers a
 // wave has, and the compiler spills them to VGPR lanes and reads them back
 // with v_readlane inside the rounds.
-template <int NR, int NV>
+template <int NR, int NV, int FIRST = 1>
 struct RoundKeys {
-    static constexpr int V = NV < NR - 1 ? NV : NR - 1;
+    static constexpr int V = NV < NR - FIRST ? NV : NR - FIRST;
     const uint32_t *rk;
     uint32_t v[V > 0 ? 4 * V : 1];
     __device__ __forceinline__ explicit RoundKeys(const uint32_t *__restrict__ k) : rk(k) {
 #pragma unroll
         for (int i = 0; i < 4 * V; i++)
-            v[i] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)k[4 + i], 0xE4, 0xF, 0xF, false);
+            v[i] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)k[4 * FIRST + i], 0xE4, 0xF, 0xF,
+                                                         false);
     }
     // Round r's four words (r a compile-time constant after unrolling).
     __device__ __forceinline__ const uint32_t *operator[](int r) const {
-        return r >= 1 && r <= V ? v + 4 * (r - 1) : rk + 4 * r;
+        return r >= FIRST && r < FIRST + V ? v + 4 * (r - FIRST) : rk + 4 * r;
     }
 };
 
 // Rounds whose keys the 1024-thread tile and per-request kernels hold in
 // vector registers, per side: the fewest that leave no scalar-register spills
-// with two blocks per lane (113 VGPRs for CTR, 103 for decryption, of the 128
-// such workgroups allow).  Measured about 1% faster on every key size and
-// side than all-scalar keys with their spills.
+// with two blocks per lane (113 VGPRs for plain CTR, 103 for decryption, of
+// the 128 such workgroups allow).  Measured about 1% faster on every key size
+// and side than all-scalar keys with their spills.  CTR tiles with shared
+// heads hold rounds 3..7 (rounds 1 and 2 come from the heads); they spill
+// some loop state to VGPR lanes, read back once per step, and 5 measured
+// ahead of 3 and 4.
 constexpr int TILE_NV_CTR = 5;
 constexpr int TILE_NV_DEC = 8;
 
@@ -281,6 +285,143 @@ __device__ __forceinline__ void ctr_unit(const uint32_t *lds, uint32_t L0,
     }
 }
 
+// ------------------------------------------- CTR tiles, shared first rounds
+//
+// Counter blocks differ only in byte 15 until a carry.  With the initial
+// state words s0..s3 (counter byte 15 is byte 3 of s3), round 1 gives
+//   t0 = U0 ^ Te3[s3.b3],  t1, t2, t3 independent of byte 15,
+// and round 2 takes one byte of t0 per output column:
+//   u0 = P0 ^ Te0[t0.b0], u1 = P1 ^ Te3[t0.b3], u2 = P2 ^ Te2[t0.b2],
+//   u3 = P3 ^ Te1[t0.b1],
+// where U0 and P0..P3 depend only on counter bytes 0..14 (and the key).  A
+// group of 256 consecutive counters sees at most two values of those bytes
+// (one carry out of byte 15).  Once per group the wave computes U0, P0..P3
+// for both (heads A and B) with scalar loads from the table image in device
+// memory, off the LDS pipe, and each lane takes the head of its block:
+// rounds 1 and 2 cost 5 LDS lookups per block instead of 32.  (Caching the
+// counter's constant part across the first rounds is Bernstein and
+// Schwabe's idea, "New AES software speed records", INDOCRYPT 2008.)
+
+// U0, P0..P3 for the counter blocks whose bits 8..63 equal h.  n0, n1: nonce
+// words already XORed with round key 0; te: Te0..Te3 in device memory.
+__device__ __forceinline__ void ctr_head(const uint32_t *__restrict__ te, uint32_t n0, uint32_t n1,
+                                         uint64_t h, const uint32_t *__restrict__ rk,
+                                         uint32_t out[5]) {
+    const uint64_t c = h << 8;
+    const uint32_t s0 = n0, s1 = n1;
+    const uint32_t s2 = __builtin_bswap32((uint32_t)(c >> 32)) ^ rk[2];
+    const uint32_t s3 = __builtin_bswap32((uint32_t)c) ^ rk[3];  // byte 3 is not used
+    auto T = [te](int t, uint32_t w, int k) { return te[t * 256 + ((w >> (8 * k)) & 255u)]; };
+    const uint32_t *k1 = rk + 4, *k2 = rk + 8;
+    const uint32_t t1 = T(0, s1, 0) ^ T(1, s2, 1) ^ T(2, s3, 2) ^ T(3, s0, 3) ^ k1[1];
+    const uint32_t t2 = T(0, s2, 0) ^ T(1, s3, 1) ^ T(2, s0, 2) ^ T(3, s1, 3) ^ k1[2];
+    const uint32_t t3 = T(0, s3, 0) ^ T(1, s0, 1) ^ T(2, s1, 2) ^ T(3, s2, 3) ^ k1[3];
+    out[0] = T(0, s0, 0) ^ T(1, s1, 1) ^ T(2, s2, 2) ^ k1[0];
+    out[1] = T(1, t1, 1) ^ T(2, t2, 2) ^ T(3, t3, 3) ^ k2[0];
+    out[2] = T(0, t1, 0) ^ T(1, t2, 1) ^ T(2, t3, 2) ^ k2[1];
+    out[3] = T(0, t2, 0) ^ T(1, t3, 1) ^ T(3, t1, 3) ^ k2[2];
+    out[4] = T(0, t3, 0) ^ T(2, t1, 2) ^ T(3, t2, 3) ^ k2[3];
+}
+
+// Both heads of the counters ctr0 + g .. ctr0 + g + n - 1 (n <= 256): A for
+// those before the carry out of byte 15, D = A ^ B (zero without a carry).
+__device__ __forceinline__ void ctr_heads(const uint32_t *__restrict__ te, uint32_t n0, uint32_t n1,
+                                          uint64_t cf, uint32_t n,
+                                          const uint32_t *__restrict__ rk, uint32_t A[5],
+                                          uint32_t D[5]) {
+    ctr_head(te, n0, n1, cf >> 8, rk, A);
+    // Keep the two heads' scalar loads apart (scalar registers are short).
+    __builtin_amdgcn_sched_barrier(0);
+    if (((uint32_t)cf & 255u) + n - 1u >= 256u) {
+        // Bits 8..63 one higher (mod 2^56, as the 64-bit counter wraps).
+        uint32_t B[5];
+        ctr_head(te, n0, n1, (cf >> 8) + 1u, rk, B);
+#pragma unroll
+        for (int j = 0; j < 5; j++)
+            D[j] = A[j] ^ B[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < 5; j++)
+            D[j] = 0u;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// One step of ctr_unit_head: blocks base + 64 i + lane; lo0 = the low byte of
+// the heads' first counter plus base minus that counter's block.
+template <int NB, int NR, int NV>
+__device__ __forceinline__ void ctr_head_step(const uint32_t *lds, uint32_t L0, uint32_t lane,
+                                              const RoundKeys<NR, NV, 3> &K,
+                                              const uint32_t A[5], const uint32_t D[5],
+                                              uint32_t lo0, uint32_t rk3, uint32_t base,
+                                              uint32_t nbytes, const uint8_t *src, uint8_t *dst) {
+    uint32_t s[NB][4], x[NB][4];
+#pragma unroll
+    for (int i = 0; i < NB; i++) {
+        const uint32_t lo = lo0 + 64u * i + lane;  // < 512
+        const uint32_t m = lo >= 256u ? ~0u : 0u;  // this block takes head B
+        const uint32_t t0 = (A[0] ^ (D[0] & m)) ^ tlook<3, 3>(lds, (lo << 24) ^ rk3, L0);
+        s[i][0] = (A[1] ^ (D[1] & m)) ^ tlook<0, 0>(lds, t0, L0);
+        s[i][1] = (A[2] ^ (D[2] & m)) ^ tlook<3, 3>(lds, t0, L0);
+        s[i][2] = (A[3] ^ (D[3] & m)) ^ tlook<2, 2>(lds, t0, L0);
+        s[i][3] = (A[4] ^ (D[4] & m)) ^ tlook<1, 1>(lds, t0, L0);
+        load_block(src, base + 64u * i + lane, nbytes, x[i]);
+    }
+#pragma unroll
+    for (int r = 3; r < NR; r++) {
+#pragma unroll
+        for (int i = 0; i < NB; i++)
+            enc_round(lds, s[i], K[r], L0);
+    }
+#pragma unroll
+    for (int i = 0; i < NB; i++) {
+        uint32_t o[4];
+        enc_last(lds, s[i], K[NR], L0, x[i], o);
+        store_block(dst, base + 64u * i + lane, nbytes, o);
+    }
+}
+
+// ctr_unit with rounds 1 and 2 from the shared heads (same output).  AES-128
+// and AES-192 compute the heads once per group of 256 counters (a 4 KiB
+// unit: once); AES-256 once per step, in a single loop: with the heads live
+// across steps its scalar round keys no longer fit beside them, and the
+// nested loop measured 10% slower than the per-step form, which is 4%
+// faster than no heads at all.
+template <int NB, int NR, int NV = 0>
+__device__ __forceinline__ void ctr_unit_head(const uint32_t *lds, uint32_t L0, uint32_t lane,
+                                              const Unit &un, const uint32_t *__restrict__ rk,
+                                              const uint32_t *__restrict__ te, const uint8_t *in,
+                                              uint8_t *out) {
+    static_assert(256 % (64 * NB) == 0, "steps tile a group of 256 counters");
+    const RoundKeys<NR, NV, 3> K(rk);
+    const uint32_t nbytes = un.nbytes;
+    const uint32_t nblk = (nbytes + 15u) >> 4;
+    const uint64_t ctr0 = ((uint64_t)un.w[3] << 32) | un.w[2];
+    const uint32_t n0 = un.w[0] ^ rk[0];
+    const uint32_t n1 = un.w[1] ^ rk[1];
+    const uint8_t *src = in + un.off;
+    uint8_t *dst = out + un.off;
+    uint32_t A[5], D[5];
+    if constexpr (NR <= 12) {
+        for (uint32_t g = 0; g < nblk; g += 256u) {
+            const uint64_t cf = ctr0 + g;  // the group's first counter (wave-uniform)
+            const uint32_t gend = nblk - g < 256u ? nblk : g + 256u;
+            ctr_heads(te, n0, n1, cf, gend - g, rk, A, D);
+            for (uint32_t base = g; base < gend; base += 64u * NB)
+                ctr_head_step<NB, NR, NV>(lds, L0, lane, K, A, D,
+                                          ((uint32_t)cf & 255u) + (base - g), rk[3], base,
+                                          nbytes, src, dst);
+        }
+    } else {
+        for (uint32_t base = 0; base < nblk; base += 64u * NB) {
+            const uint64_t cf = ctr0 + base;  // the step's first counter (wave-uniform)
+            ctr_heads(te, n0, n1, cf, 64u * NB, rk, A, D);
+            ctr_head_step<NB, NR, NV>(lds, L0, lane, K, A, D, (uint32_t)cf & 255u, rk[3], base,
+                                      nbytes, src, dst);
+        }
+    }
+}
+
 // SP 800-38A 6.1: ECB encryption, every block on its own (whole blocks).
 template <int NB, int NR, int NV = 0>
 __device__ __forceinline__ void ecb_enc_unit(const uint32_t *lds, uint32_t L0, uint32_t lane,
@@ -318,11 +459,13 @@ __device__ __forceinline__ void ecb_enc_unit(const uint32_t *lds, uint32_t L0, u
 
 // Key checks and round-count dispatch for one encryption-table tile (CTR
 // or ECB encryption; wave-uniform).
+// With te (Te0..Te3 in device memory) CTR units take the shared-head path.
 template <int NB, int NV = 0>
 __device__ __forceinline__ void run_ctr_unit(const uint32_t *lds, uint32_t L0,
                                              uint32_t lane, const Unit &un,
                                              const aes_schedule_t *__restrict__ sched,
-                                             uint32_t n_sched, const uint8_t *in, uint8_t *out) {
+                                             uint32_t n_sched, const uint8_t *in, uint8_t *out,
+                                             const uint32_t *__restrict__ te = nullptr) {
     const uint32_t key = un.meta & META_KEY_MASK;
     if (key >= n_sched)
         return;
@@ -335,6 +478,15 @@ __device__ __forceinline__ void run_ctr_unit(const uint32_t *lds, uint32_t L0,
             ecb_enc_unit<NB, 12, NV>(lds, L0, lane, un, ks->ek, in, out);
         else if (nr == 14)
             ecb_enc_unit<NB, 14, NV>(lds, L0, lane, un, ks->ek, in, out);
+        return;
+    }
+    if (te) {
+        if (nr == 10)
+            ctr_unit_head<NB, 10, NV>(lds, L0, lane, un, ks->ek, te, in, out);
+        else if (nr == 12)
+            ctr_unit_head<NB, 12, NV>(lds, L0, lane, un, ks->ek, te, in, out);
+        else if (nr == 14)
+            ctr_unit_head<NB, 14, NV>(lds, L0, lane, un, ks->ek, te, in, out);
         return;
     }
     if (nr == 10)

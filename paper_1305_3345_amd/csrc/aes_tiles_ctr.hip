@@ -1,8 +1,9 @@
 // aes_tiles_ctr.hip -- encryption-side tile kernels (CTR and ECB encryption).
-// Built with LLVM's max-ILP instruction scheduler, which keeps more table
-// lookups of the two blocks per lane in flight; measured 3% faster than the
-// default scheduler on 4 KiB AES-128 and AES-256 pages (each variant's
-// launches interleaved in one process).
+// Built with LLVM's default instruction scheduler.  Before CTR tiles computed
+// the first two rounds' shared part once per group of counters, the max-ILP
+// scheduler was 3% faster here; with that shared part it leaves round keys
+// spilled to scratch, and the default scheduler gives the fastest CTR tiles
+// on every key size (ECB encryption tiles lose 1-2% against max-ILP).
 #include "tile_kernel.h"
 
 namespace aesgpu {

@@ -56,7 +56,7 @@ __global__ __launch_bounds__(WG) void k_tiles(const Unit *__restrict__ units, ui
             run_dec_unit<NB, TILE_NV_DEC>(lds, L0, L2, lane, un, preds ? preds + u : nullptr,
                                           sched, n_sched, in, out);
         else
-            run_ctr_unit<NB, TILE_NV_CTR>(lds, L0, lane, un, sched, n_sched, in, out);
+            run_ctr_unit<NB, TILE_NV_CTR>(lds, L0, lane, un, sched, n_sched, in, out, timg);
         c = __builtin_amdgcn_readfirstlane(got);
     }
     if (c == range + wpb - 1 && lane == 0)
