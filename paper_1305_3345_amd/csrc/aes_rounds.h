@@ -207,10 +207,21 @@ __device__ __forceinline__ void store_block(uint8_t *dst, uint32_t b, uint32_t n
 
 // ------------------------------------------------------------ round keys
 
-// Round keys of one schedule for the tile loops.  Keys of rounds 1..NV are
-// copied into vector registers once per unit (a DPP move with the identity
-// lane pattern gives the compiler a per-lane value, so it stays in a VGPR);
-// the others are read from the schedule into scalar registers.  With every
+// A wave-uniform word copied into a vector register with one v_mov_b32.
+// Written as inline assembly, the result is opaque to the compiler, which
+// therefore keeps it in that VGPR instead of folding it back into the scalar
+// register it came from.  (An identity-pattern DPP move does the same in the
+// compiler's terms but costs three VALU ops: the scalar-to-vector move, the
+// tied "old" operand and the DPP move.)
+__device__ __forceinline__ uint32_t to_vgpr(uint32_t k) {
+    uint32_t v;
+    asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(k));
+    return v;
+}
+
+// Round keys of one schedule for the tile loops.  Keys of rounds
+// FIRST..FIRST+NV-1 are copied into vector registers once per unit
+// (to_vgpr); the others are read from the schedule into scalar registers.  With every
 // round key scalar, keys plus the loop state exceed the scalar registers a
 // wave has, and the compiler spills them to VGPR lanes and reads them back
 // with v_readlane inside the rounds.
@@ -222,8 +233,7 @@ struct RoundKeys {
     __device__ __forceinline__ explicit RoundKeys(const uint32_t *__restrict__ k) : rk(k) {
 #pragma unroll
         for (int i = 0; i < 4 * V; i++)
-            v[i] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)k[4 * FIRST + i], 0xE4, 0xF, 0xF,
-                                                         false);
+            v[i] = to_vgpr(k[4 * FIRST + i]);
     }
     // Round r's four words (r a compile-time constant after unrolling).
     __device__ __forceinline__ const uint32_t *operator[](int r) const {
