@@ -283,11 +283,35 @@ int aes_ctx_set_config(aes_ctx_t *ctx, const aes_launch_config_t *cfg);
  * so far only when it is more than 2% faster, so knobs that do not change
  * the batch's time keep their starting values.  Leaves the chosen
  * configuration set in ctx and copies it to *best (may be NULL).  Plans
- * created afterwards use its tile size.  Errors: as aes_batch;
- * AES_ERR_OVERLAP if d_in == d_out. */
+ * created afterwards use its tile size.
+ *
+ * Tune cache: when the environment variable AESGPU_TUNE_CACHE names a file,
+ * the batch's signature (aes_tune_key) is looked up there first; a stored
+ * configuration that this build supports is set and returned without any
+ * launch (also on a host-only context).  Otherwise the tuner runs and stores
+ * its result under the signature.  The file is text, one entry per line:
+ * the signature, a TAB, and the twelve configuration fields tile_bytes ..
+ * chain_quad as decimal numbers; '#' starts a comment line; lines that do
+ * not parse are skipped; writes replace the signature's entry and go
+ * through a temporary file renamed over the cache.  A file that cannot be
+ * read counts as empty, one that cannot be written is left as it was.
+ *
+ * Errors: as aes_batch; AES_ERR_OVERLAP if d_in == d_out; AES_ERR_DEVICE
+ * on a host-only context without a cached entry. */
 int aes_tune(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_scheds,
              uint64_t buf_bytes, const aes_schedule_t *d_scheds, const uint8_t *d_in,
              uint8_t *d_out, uint32_t iters, aes_launch_config_t *best);
+
+/* The tune cache's signature of a batch, as a NUL-terminated string in buf
+ * (cap bytes): the device architecture and compute-unit count of ctx ("host"
+ * and 0 for a host-only context), and size classes 2^k = floor(log2) ("-" for
+ * zero) of the request count, of the requests per op (CBC-enc, CBC-dec,
+ * CTR, ECB-enc, ECB-dec), of the total payload, of the shortest and longest
+ * non-empty request, and of n_scheds.  *len_out (may be NULL) receives the
+ * signature's length without the NUL.  Errors: AES_ERR_ARG for a NULL
+ * argument or cap <= length (then *len_out still holds the length). */
+int aes_tune_key(const aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_scheds,
+                 char *buf, size_t cap, size_t *len_out);
 
 /* ------------------------------------------------ per-request launches, graphs */
 

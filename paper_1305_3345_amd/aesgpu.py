@@ -104,6 +104,8 @@ def lib():
             "aes_ctx_get_config": (i32, [p, p]),
             "aes_ctx_set_config": (i32, [p, p]),
             "aes_tune": (i32, [p, p, u64, u32, u64, p, p, p, u32, p]),
+            "aes_tune_key": (i32, [p, p, u64, u32, p, ctypes.c_size_t,
+                                   ctypes.POINTER(ctypes.c_size_t)]),
             "aes_request_launch": (i32, [p, p, u32, p, p, u64, p, p]),
             "aes_request_launches": (i32, [p, p, u32, p, p, u64, p, u64, p]),
             "aes_plan_graph": (i32, [p, p, p, p, ctypes.POINTER(p)]),
@@ -333,7 +335,9 @@ class Plan:
 
 def tune(ctx: Context, reqs: np.ndarray, d_scheds, d_in, d_out, iters: int = 5,
          buf_bytes: int | None = None, n_scheds: int | None = None) -> dict:
-    """aes_tune: sets and returns the fastest launch configuration for reqs."""
+    """aes_tune: sets and returns the fastest launch configuration for reqs
+    (from the file named by AESGPU_TUNE_CACHE when it holds this batch's
+    signature)."""
     reqs = np.ascontiguousarray(reqs, dtype=REQ_DTYPE)
     best = np.zeros(1, CONFIG_DTYPE)
     bb = _nbytes(d_in) if buf_bytes is None else buf_bytes
@@ -341,6 +345,18 @@ def tune(ctx: Context, reqs: np.ndarray, d_scheds, d_in, d_out, iters: int = 5,
                           _sched_count(d_scheds, n_scheds), bb, _ptr(d_scheds), _ptr(d_in),
                           _ptr(d_out), iters, best.ctypes.data), "aes_tune")
     return {k: int(best[0][k]) for k in CONFIG_DTYPE.names if k != "reserved"}
+
+
+def tune_key(ctx: Context, reqs: np.ndarray, n_scheds: int) -> str:
+    """aes_tune_key: the tune cache's signature of a batch."""
+    reqs = np.ascontiguousarray(reqs, dtype=REQ_DTYPE)
+    n = ctypes.c_size_t(0)
+    lib().aes_tune_key(ctx.handle, reqs.ctypes.data, reqs.size, n_scheds, None, 0,
+                       ctypes.byref(n))
+    buf = ctypes.create_string_buffer(n.value + 1)
+    _check(lib().aes_tune_key(ctx.handle, reqs.ctypes.data, reqs.size, n_scheds, buf,
+                              n.value + 1, None), "aes_tune_key")
+    return buf.value.decode()
 
 
 def request_launch(ctx: Context, d_scheds, d_in, d_out, req, buf_bytes: int | None = None,

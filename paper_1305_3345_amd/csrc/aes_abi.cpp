@@ -13,10 +13,12 @@
 #include <algorithm>
 #include <memory>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "host_pool.h"
 #include "internal.h"
+#include "tune_cache.h"
 
 using namespace aesgpu;
 
@@ -303,6 +305,7 @@ struct Slot {
 struct aes_ctx {
     int device = AES_DEVICE_NONE;
     int n_cu = 0;
+    char arch[32] = "host";  // device architecture (gcnArchName up to ':'), for the tune cache
     uint32_t *d_timg = nullptr;
     static constexpr int N_SLOTS = 4;
     Slot slots[N_SLOTS];
@@ -837,6 +840,10 @@ int aes_ctx_create(int hip_device, aes_ctx_t **out) {
             return hip_fail(e);
         }
         ctx->n_cu = prop.multiProcessorCount;
+        size_t an = strcspn(prop.gcnArchName, ":");
+        an = an < sizeof(ctx->arch) - 1 ? an : sizeof(ctx->arch) - 1;
+        memcpy(ctx->arch, prop.gcnArchName, an);
+        ctx->arch[an] = '\0';
         uint32_t img[TIMG_WORDS];
         make_table_image(img);
         if (hipMalloc((void **)&ctx->d_timg, sizeof(img)) != hipSuccess) {
@@ -1330,6 +1337,19 @@ int aes_tune(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_
         return AES_ERR_OVERLAP;  // repeated runs must not feed on their own output
     if ((st = validate(reqs, n_reqs, n_scheds, buf_bytes)))
         return st;
+    // The tune cache: a stored configuration for a batch of this shape is
+    // applied without timing (if this build still supports it).
+    const char *cache = getenv("AESGPU_TUNE_CACHE");
+    std::string sig;
+    if (cache && *cache) {
+        sig = tune_signature(ctx->arch, ctx->n_cu, reqs, n_reqs, n_scheds);
+        aes_launch_config_t c;
+        if (tune_cache_lookup(cache, sig, &c) && aes_ctx_set_config(ctx, &c) == AES_OK) {
+            if (best_out)
+                aes_ctx_get_config(ctx, best_out);
+            return AES_OK;
+        }
+    }
     if (ctx->device == AES_DEVICE_NONE)
         return AES_ERR_DEVICE;
     HIP_TRY(hipSetDevice(ctx->device));
@@ -1426,8 +1446,23 @@ int aes_tune(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_
     (void)aes_ctx_set_config(ctx, &best);
     if (st)
         return st;
+    if (cache && *cache)
+        (void)tune_cache_store(cache, sig, best);  // a cache that cannot be written is skipped
     if (best_out)
         *best_out = best;
+    return AES_OK;
+}
+
+int aes_tune_key(const aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_scheds,
+                 char *buf, size_t cap, size_t *len_out) {
+    if (!ctx || (n_reqs && !reqs) || (cap && !buf))
+        return AES_ERR_ARG;
+    const std::string sig = tune_signature(ctx->arch, ctx->n_cu, reqs, n_reqs, n_scheds);
+    if (len_out)
+        *len_out = sig.size();
+    if (cap < sig.size() + 1)
+        return AES_ERR_ARG;
+    memcpy(buf, sig.c_str(), sig.size() + 1);
     return AES_OK;
 }
 

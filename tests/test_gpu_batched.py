@@ -184,6 +184,47 @@ def test_tune_then_plan(fresh):
         a.tune(fresh, wl.reqs, d_s, d_in, d_in, iters=1)
 
 
+def test_tune_cache_store_then_hit(tmp_path, monkeypatch):
+    """With AESGPU_TUNE_CACHE set, a tuning run stores its result under the
+    batch's signature; a new context tuning a batch of the same shape gets the
+    stored configuration without a tuning run (the file is not rewritten),
+    and its plan still matches the oracle."""
+    print("[gpu] tune cache", flush=True)
+    import time
+    a = ag()
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("AESGPU_TUNE_CACHE", str(path))
+    wl = mixed_workload(n=200, max_pages=16)
+    inp = wl.data()
+    d_s = device_schedules(wl)
+    d_in = torch.from_numpy(inp).cuda()
+    d_out = torch.empty_like(d_in)
+    c1 = a.Context(0)
+    c1.set_config(ctr_nb=1, ctr_wg=512)  # a start the tuner may or may not keep
+    t0 = time.perf_counter()
+    best = a.tune(c1, wl.reqs, d_s, d_in, d_out, iters=2)
+    t_tune = time.perf_counter() - t0
+    sig = a.tune_key(c1, wl.reqs, wl.keys.shape[0])
+    assert sig.startswith("arch=gfx")
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].split("\t")[0] == sig
+    assert [int(x) for x in lines[0].split("\t")[1].split()] == [
+        best[k] for k in ("tile_bytes", "ctr_nb", "ctr_wg", "dec_nb", "dec_wg", "chain_lanes",
+                          "chain_wg", "mixed_nb", "fuse", "grid", "ctr_variant", "chain_quad")]
+    mtime = path.stat().st_mtime_ns
+    c2 = a.Context(0)
+    t0 = time.perf_counter()
+    hit = a.tune(c2, wl.reqs, d_s, d_in, d_out, iters=2)
+    t_hit = time.perf_counter() - t0
+    assert hit == best and c2.get_config() == best
+    assert path.stat().st_mtime_ns == mtime
+    print(f"[gpu] tuning {t_tune * 1e3:.1f} ms, cache hit {t_hit * 1e3:.2f} ms", flush=True)
+    assert t_hit < t_tune
+    check(run_gpu(c2, wl, inp, form="plan"), run_oracle(wl, inp), f"cached config {hit}")
+    c1.close()
+    c2.close()
+
+
 def test_config3_full_size_sampled(fresh):
     """The full config-3 batch (10,000 requests, about 1.75 GiB) in one fused
     launch; 200 sampled requests plus the longest CBC-encrypt chain are checked
