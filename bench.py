@@ -26,6 +26,18 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 UNIT_BYTES = 32  # one work-unit record read per tile
 SCHED_BYTES = 512
+# Conflict-free ds_read_b32 lane-gathers per second on the whole chip, as a
+# probe of dependent ds_read_b32 chains measured it (31.0 per clock per CU,
+# 97% of the 32 addresses the LDS serves per clock).
+LDS_GATHER_CEILING = 1.83e13
+
+
+def lds_gathers_per_block(run: str) -> int:
+    """Table lookups (LDS gathers) per 16-byte block of a run such as
+    "ctr_128" or "cbc_dec_256": 16 per round; CTR's first two rounds take 5
+    instead of 32 (their counter-invariant part comes from scalar loads)."""
+    nr = {128: 10, 192: 12, 256: 14}[int(run.rsplit("_", 1)[1])]
+    return 16 * nr - (27 if run.startswith("ctr") else 0)
 
 
 def parse():
@@ -734,10 +746,12 @@ def main():
                          "gbs_payload": round(payload / avg / 1e6, 1),
                          "hbm_frac": round(algo / avg / 1e6 / HBM_PEAK_GBS, 4),
                          "frac_of_copy": round(algo / avg / 1e6 / copy_gbs, 4)}
-        pk = per_kernel.setdefault(kname, {"ms_total": 0.0, "launches": 0, "algo_bytes": 0})
+        pk = per_kernel.setdefault(kname, {"ms_total": 0.0, "launches": 0, "algo_bytes": 0,
+                                           "gathers": 0})
         pk["ms_total"] += sum(ms)
         pk["launches"] += len(ms)
         pk["algo_bytes"] += algo * len(ms)
+        pk["gathers"] += payload // 16 * lds_gathers_per_block(name) * len(ms)
     dom = max(per_kernel, key=lambda k: per_kernel[k]["ms_total"])
     d = per_kernel[dom]
     avg_ms = d["ms_total"] / d["launches"]
@@ -748,6 +762,13 @@ def main():
                 "traffic": profiled_traffic(f"aesgpu::{dom}", n_pages),
                 "kernel": f"aesgpu::{dom}", "avg_launch_ms": round(avg_ms, 4),
                 "algo_bytes_per_launch": int(algo_per_launch)}
+    # The ceiling that binds the table rounds: LDS gathers (one ds_read_b32
+    # lane per table lookup) against the rate a ds_read_b32 probe measured.
+    g_rate = d["gathers"] / d["launches"] / avg_ms * 1e3
+    roofline["lds_gathers"] = {"achieved": float(f"{g_rate:.4g}"), "ceiling": LDS_GATHER_CEILING,
+                               "unit": "lane-gathers/s",
+                               "frac": round(g_rate / LDS_GATHER_CEILING, 4),
+                               "per_launch": int(d["gathers"] / d["launches"])}
 
     # Host-metadata single-call form: validation, planning and the unit-table
     # upload happen inside every call (end-to-end, reported beside the value).

@@ -275,13 +275,16 @@ int aes_ctx_get_config(const aes_ctx_t *ctx, aes_launch_config_t *cfg);
 int aes_ctx_set_config(aes_ctx_t *ctx, const aes_launch_config_t *cfg);
 
 /* Autotuner: times plan launches of reqs on the caller's buffers (d_in must
- * differ from d_out; d_out is overwritten with the batch's result) for tile
- * sizes, tile-kernel shapes, the fused kernel's blocks per lane, chain lanes
- * or four-lane chains, the fusion switch and (for batches with CTR requests)
- * the CTR variant by coordinate descent (median of iters launches each),
- * starting from ctx's current configuration; a candidate replaces the best
- * so far only when it is more than 2% faster, so knobs that do not change
- * the batch's time keep their starting values.  Leaves the chosen
+ * differ from d_out; d_out is overwritten with the batch's result) by
+ * coordinate descent from ctx's current configuration (each candidate: one
+ * untimed launch, then the median of iters timed launches), one knob at a
+ * time and only over knobs the batch's launch uses: the tile size (batches
+ * with tiles), the fusion switch (chains mixed with tiles), the tile-kernel
+ * shapes (unfused launches of table tiles), the fused kernel's blocks per
+ * lane (fused launches), chain lanes or four-lane chains (batches with
+ * CBC-encrypt chains) and the CTR variant (batches with CTR requests).  A
+ * candidate replaces the best so far only when it is more than 2% faster,
+ * so knobs that do not change the batch's time keep their starting values.  Leaves the chosen
  * configuration set in ctx and copies it to *best (may be NULL).  Plans
  * created afterwards use its tile size.
  *

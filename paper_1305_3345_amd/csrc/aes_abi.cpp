@@ -1387,56 +1387,81 @@ int aes_tune(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_
         }
         return AES_OK;
     };
-    // Coordinate descent: tile size, then each kernel's shape, then the chain
-    // lanes, the fusion switch and the CTR variant, each from the best point
-    // so far.
+    // Coordinate descent from the starting configuration, one knob at a time
+    // from the best point so far, and only over knobs the batch's launch uses
+    // (a knob the launch ignores would be set by timing noise alone): tile
+    // size; the fusion switch (batches mixing CBC-encrypt chains with tiles);
+    // tile-kernel shapes (unfused launches with tiles); the fused kernel's
+    // blocks per lane (fused launches); chain mode (batches with chains); the
+    // CTR variant (batches with CTR requests).
     aes_launch_config_t c = best;
     st = trial(c);
+    if (!st && !plan)
+        st = AES_ERR_ARG;  // the context's own configuration did not apply
+    if (st) {
+        aes_plan_destroy(plan);
+        (void)aes_ctx_set_config(ctx, &best);
+        return st;
+    }
+    // Which unit kinds the batch has (the plan is rebuilt by later trials;
+    // only whether each kind is present is kept, which no knob changes).
+    const bool has_dec = !plan->p.dec.empty();
+    const bool has_ctr = plan->p.ctr.size() > plan->p.n_ecb;
+    const bool has_ecb_enc = plan->p.n_ecb > 0;
+    const bool has_chains = !plan->p.chains.empty();
+    const bool has_tiles = has_dec || has_ctr || has_ecb_enc;
+    // Whether the table tile kernels run, and whether one fused launch takes
+    // the batch, under k (as launch_planned decides: the bitsliced variant
+    // launches the CTR tiles on their own).
+    auto table_tiles = [&](const aes_launch_config_t &k) {
+        return has_dec || has_ecb_enc || (has_ctr && k.ctr_variant != AES_CTR_BITSLICE);
+    };
+    auto fused = [&](const aes_launch_config_t &k) {
+        const bool ctr_tab = has_ecb_enc || (has_ctr && k.ctr_variant != AES_CTR_BITSLICE);
+        const int kinds = (int)has_dec + (int)ctr_tab + (int)has_chains;
+        return k.fuse && has_chains && kinds > 1;
+    };
     const uint32_t tiles[] = {4096, 8192, 16384};
     for (uint32_t t : tiles) {
-        if (st)
+        if (st || !has_tiles)
             break;
         c = best;
         c.tile_bytes = t;
         st = trial(c);
     }
+    for (uint32_t f = 0; f <= 1 && !st && has_chains && has_tiles; f++) {
+        c = best;
+        c.fuse = f;
+        st = trial(c);
+    }
     const uint32_t shapes[][2] = {{1, 1024}, {2, 1024}, {2, 512}, {4, 512}, {4, 256}, {1, 512}};
     for (auto &sh : shapes) {
-        if (st)
+        if (st || fused(best) || !table_tiles(best))
             break;
         c = best;
         c.ctr_nb = c.dec_nb = sh[0];
         c.ctr_wg = c.dec_wg = sh[1];
         st = trial(c);
     }
-    for (uint32_t mnb = 1; mnb <= 2 && !st; mnb++) {
+    for (uint32_t mnb = 1; mnb <= 2 && !st && fused(best); mnb++) {
         c = best;
         c.mixed_nb = mnb;
         st = trial(c);
     }
     const uint32_t lanes[] = {16, 32, 64};
     for (uint32_t l : lanes) {
-        if (st)
+        if (st || !has_chains)
             break;
         c = best;
         c.chain_lanes = l;
         c.chain_quad = 0;
         st = trial(c);
     }
-    if (!st) {  // four lanes per chain
+    if (!st && has_chains) {  // four lanes per chain
         c = best;
         c.chain_quad = 1;
         st = trial(c);
     }
-    for (uint32_t f = 0; f <= 1 && !st; f++) {
-        c = best;
-        c.fuse = f;
-        st = trial(c);
-    }
-    // The CTR kernel variant, when the batch has CTR requests.
-    bool has_ctr = false;
-    for (uint64_t i = 0; i < n_reqs && !has_ctr; i++)
-        has_ctr = reqs[i].op == AES_OP_CTR && reqs[i].length;
     for (uint32_t v = AES_CTR_TABLE; v <= AES_CTR_BITSLICE && has_ctr && !st; v++) {
         c = best;
         c.ctr_variant = v;

@@ -184,6 +184,36 @@ def test_tune_then_plan(fresh):
         a.tune(fresh, wl.reqs, d_s, d_in, d_in, iters=1)
 
 
+def test_tune_leaves_unused_knobs():
+    """The tuner tries only knobs the batch's launch uses: with chains and
+    tiles in one fused launch the tile-kernel shapes keep their starting
+    values; a batch without chains keeps its chain and fused-kernel
+    settings."""
+    print("[gpu] tuner skips unused knobs", flush=True)
+    a = ag()
+    shapes = ("ctr_nb", "ctr_wg", "dec_nb", "dec_wg")
+    wl = mixed_workload(n=120, max_pages=8)
+    inp = wl.data()
+    d_s = device_schedules(wl)
+    d_in = torch.from_numpy(inp).cuda()
+    d_out = torch.empty_like(d_in)
+    c = a.Context(0)
+    c.set_config(ctr_nb=1, ctr_wg=512, dec_nb=1, dec_wg=512)
+    start = c.get_config()
+    best = a.tune(c, wl.reqs, d_s, d_in, d_out, iters=1)
+    if best["fuse"]:
+        assert {k: best[k] for k in shapes} == {k: start[k] for k in shapes}
+    c.close()
+    par = wl.reqs[wl.reqs["op"] != workloads.OP_CBC_ENC]
+    c = a.Context(0)
+    c.set_config(chain_lanes=32, chain_quad=0, mixed_nb=2)
+    best = a.tune(c, par, d_s, d_in, d_out, iters=1)
+    assert (best["chain_lanes"], best["chain_quad"], best["mixed_nb"]) == (32, 0, 2)
+    check(run_gpu(c, wl, inp, form="plan", reqs=par), run_oracle(wl, inp, reqs=par),
+          f"tuned {best}")
+    c.close()
+
+
 def test_tune_cache_store_then_hit(tmp_path, monkeypatch):
     """With AESGPU_TUNE_CACHE set, a tuning run stores its result under the
     batch's signature; a new context tuning a batch of the same shape gets the
