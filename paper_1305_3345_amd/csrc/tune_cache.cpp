@@ -15,6 +15,7 @@
 #include <string.h>
 #include <unistd.h>
 
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -158,7 +159,11 @@ bool tune_cache_store(const char *path, const std::string &sig, const aes_launch
     for (int i = 0; i < N_FIELDS; i++)
         entry += (i ? " " : "") + std::to_string(f[i]);
     keep.push_back(entry);
-    const std::string tmp = std::string(path) + ".tmp." + std::to_string((long)getpid());
+    // Unique per process and call: two threads (each with its own context)
+    // may store at the same time; each renames only its own complete file.
+    static std::atomic<uint64_t> seq{0};
+    const std::string tmp = std::string(path) + ".tmp." + std::to_string((long)getpid()) + "." +
+                            std::to_string(seq.fetch_add(1, std::memory_order_relaxed));
     FILE *fp = fopen(tmp.c_str(), "w");
     if (!fp)
         return false;

@@ -118,3 +118,36 @@ def test_validation_precedes_cache(ag, hctx, tmp_path, monkeypatch):
     path.write_text(entry(ag.tune_key(hctx, reqs, 16), hctx.get_config()) + "\n")
     monkeypatch.setenv("AESGPU_TUNE_CACHE", str(path))
     assert raw_tune(ag, hctx, reqs)[0] == ag.AES_ERR_RANGE
+
+
+
+def test_concurrent_hits(ag, tmp_path, monkeypatch):
+    """Eight threads, each with its own host-only context and batch shape,
+    look their entries up in one cache file at the same time: every call hits
+    and sets its own entry's configuration."""
+    import threading
+    ctxs = [ag.Context(ag.AES_DEVICE_NONE) for _ in range(8)]
+    reqs = [pages_reqs(1 << (4 + i)) for i in range(8)]
+    sigs = [ag.tune_key(c, r, 16) for c, r in zip(ctxs, reqs)]
+    assert len(set(sigs)) == 8
+    base = ctxs[0].get_config()
+    cfgs = [dict(base, chain_lanes=8 * (i + 1)) for i in range(8)]
+    path = tmp_path / "tune.txt"
+    path.write_text("".join(entry(s, c) + "\n" for s, c in zip(sigs, cfgs)))
+    monkeypatch.setenv("AESGPU_TUNE_CACHE", str(path))
+    errs = []
+
+    def hit(i):
+        for _ in range(50):
+            st, got = raw_tune(ag, ctxs[i], reqs[i])
+            if st != ag.AES_OK or got != cfgs[i] or ctxs[i].get_config() != cfgs[i]:
+                errs.append((i, st))
+
+    ts = [threading.Thread(target=hit, args=(i,)) for i in range(8)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    for c in ctxs:
+        c.close()
+    assert not errs
