@@ -57,6 +57,8 @@ def parse():
                     help="skip the serving (Poisson arrivals, p50/p99) measurement")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="measured requests per arrival rate and engine")
+    ap.add_argument("--serve-warmup", type=int, default=200,
+                    help="warm-up requests before the measured ones, per rate and engine")
     ap.add_argument("--skip-host-serving", action="store_true",
                     help="skip serving with payloads in pinned host memory")
     ap.add_argument("--skip-variants", action="store_true",
@@ -505,6 +507,9 @@ def bench_serving(dev, n_measure=2000, n_warm=200):
         for engine in (aesgpu.AES_SERVE_PER_LAUNCH, aesgpu.AES_SERVE_PERSISTENT):
             done, st = replay(engine, tr.arrivals_s / rate)
             row[names[engine]] = summarize(done)
+            print(f"[serving] {names[engine]} at {frac} of saturation: p50 "
+                  f"{row[names[engine]]['p50_us']} us, p99 {row[names[engine]]['p99_us']} us",
+                  file=sys.stderr, flush=True)
             if engine == aesgpu.AES_SERVE_PERSISTENT:
                 row[names[engine]]["kernel_launches"] = st["kernel_launches"]
         rates.append(row)
@@ -801,7 +806,7 @@ def main():
 
     serving = None
     if not args.skip_serving:
-        serving = bench_serving(dev, n_measure=args.serve_requests)
+        serving = bench_serving(dev, n_measure=args.serve_requests, n_warm=args.serve_warmup)
 
     host_serving = None
     if not args.skip_host_serving:
