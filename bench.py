@@ -69,6 +69,10 @@ def parse():
                     help="skip the 8 GiB CTR stream and the 4,096 CBC-encrypt chains")
     ap.add_argument("--skip-batched", action="store_true",
                     help="skip the mixed-batch (10,000 uneven requests) measurement")
+    ap.add_argument("--batched-full-per-request", action="store_true",
+                    help="also time all 10,000 mixed requests as one launch each and as a "
+                         "graph of those launches (CBC-encrypt chains then run one after "
+                         "another: about 20 s per form)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also copy the 256 MiB input once device-to-device (a kernel of "
                          "known traffic for scaling hardware byte counters)")
@@ -155,7 +159,7 @@ def time_gpu(fn, iters, stream):
     return ms[len(ms) // 2]
 
 
-def bench_batched(dev, iters=3):
+def bench_batched(dev, iters=3, full_per_request=False):
     """The batched form: 10,000 uneven requests (4 KiB..1 MiB, mixed ops, 64
     keys of 128/256 bits) as one autotuned fused launch, against one kernel
     launch per request and a HIP graph of those launches (on the requests of
@@ -201,6 +205,29 @@ def bench_batched(dev, iters=3):
                                                            stream=stream), iters, stream)
     g_each = aesgpu.Graph.of_requests(ctx, d_s, d_in, d_out, par)
     par_graph_ms = time_gpu(lambda: g_each.launch(stream), iters, stream)
+    full = None
+    if full_per_request:
+        def once(fn):
+            a_ev = torch.cuda.Event(enable_timing=True)
+            b_ev = torch.cuda.Event(enable_timing=True)
+            a_ev.record(stream)
+            fn()
+            b_ev.record(stream)
+            b_ev.synchronize()
+            return a_ev.elapsed_time(b_ev)
+        print("[batched] all requests, one launch each", file=sys.stderr, flush=True)
+        each_ms = once(lambda: aesgpu.request_launches(ctx, d_s, d_in, d_out, wl.reqs,
+                                                       stream=stream))
+        print("[batched] all requests, graph of per-request launches", file=sys.stderr,
+              flush=True)
+        g_all = aesgpu.Graph.of_requests(ctx, d_s, d_in, d_out, wl.reqs)
+        graph_ms = once(lambda: g_all.launch(stream))
+        g_all.close()
+        full = {"per_request_launches_ms": round(each_ms, 1),
+                "per_request_graph_ms": round(graph_ms, 1),
+                "per_request_launches_gbs": round(info["payload_bytes"] / each_ms / 1e6, 2),
+                "per_request_graph_gbs": round(info["payload_bytes"] / graph_ms / 1e6, 2),
+                "note": "one timed pass each (no warm-up pass)"}
     for o in (g_plan, g_each, plan, p_long, p_par):
         o.close()
     ctx.close()
@@ -216,6 +243,7 @@ def bench_batched(dev, iters=3):
         "chain_floor_ms": round(chain_ms, 3),
         "chain_floor_request_bytes": int(longest["length"][0]),
         "chain_floor_key_bits": int(wl.key_bits[longest["key_idx"][0]]),
+        "all_requests_per_request": full,
         "parallel_subset": {
             "requests": int(par.size), "payload_bytes": par_bytes,
             "one_launch_gbs": gbs(par_bytes, par_batched_ms),
@@ -814,7 +842,7 @@ def main():
 
     batched = None
     if not args.skip_batched:
-        batched = bench_batched(dev)
+        batched = bench_batched(dev, full_per_request=args.batched_full_per_request)
 
     long_stream = None
     if not args.skip_long:
