@@ -510,6 +510,22 @@ int aes_server_calibrate(aes_server_t *srv, uint32_t key_slot, uint64_t out[5]);
  * AES_ERR_OVERLAP, AES_ERR_DEVICE (the CPU has no AES instructions). */
 int aes_host_route_crypt(const aes_schedule_t *sched, uint32_t op, const uint8_t *iv,
                          const uint8_t *src, uint8_t *dst, uint64_t length);
+
+/* A whole batch on the host route: the requests, buffer rules and results of
+ * aes_batch, with host-memory schedules (n_scheds records) and host-memory
+ * in/out buffers of buf_bytes each (in == out, or disjoint), run by
+ * n_threads host threads (0 = all hardware threads; the calling thread is
+ * one of them), each taking the next request.  A CPU baseline for the GPU
+ * forms and a CPU path for callers without a GPU; not the oracle.  Returns
+ * when every request is done.  Errors: those of aes_batch's validation
+ * (nothing runs), AES_ERR_ARG for n_threads > 1024; then, if requests failed
+ * on the host route (a schedule whose round count does not match its key
+ * size: that request's bytes stay untouched; AES_ERR_DEVICE without AES
+ * instructions), the error of the lowest-numbered failed request after the
+ * others have run. */
+int aes_host_batch(const aes_schedule_t *scheds, uint32_t n_scheds, const uint8_t *in,
+                   uint8_t *out, uint64_t buf_bytes, const aes_req_t *reqs, uint64_t n_reqs,
+                   uint32_t n_threads);
 /* Waits (up to 10 s) for in-flight requests, stops the kernel and frees
  * everything.  Returns AES_ERR_TIMEOUT if requests were still in flight. */
 int aes_server_destroy(aes_server_t *srv);

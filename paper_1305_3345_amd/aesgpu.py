@@ -106,6 +106,7 @@ def lib():
             "aes_tune": (i32, [p, p, u64, u32, u64, p, p, p, u32, p]),
             "aes_tune_key": (i32, [p, p, u64, u32, p, ctypes.c_size_t,
                                    ctypes.POINTER(ctypes.c_size_t)]),
+            "aes_host_batch": (i32, [p, u32, p, p, u64, p, u64, u32]),
             "aes_request_launch": (i32, [p, p, u32, p, p, u64, p, p]),
             "aes_request_launches": (i32, [p, p, u32, p, p, u64, p, u64, p]),
             "aes_plan_graph": (i32, [p, p, p, p, ctypes.POINTER(p)]),
@@ -345,6 +346,21 @@ def tune(ctx: Context, reqs: np.ndarray, d_scheds, d_in, d_out, iters: int = 5,
                           _sched_count(d_scheds, n_scheds), bb, _ptr(d_scheds), _ptr(d_in),
                           _ptr(d_out), iters, best.ctypes.data), "aes_tune")
     return {k: int(best[0][k]) for k in CONFIG_DTYPE.names if k != "reserved"}
+
+
+def host_batch(scheds: np.ndarray, inp: np.ndarray, out: np.ndarray, reqs: np.ndarray,
+               n_threads: int = 0):
+    """aes_host_batch: a batch on host threads with the CPU's AES instructions
+    (host schedules from expand_keys, host numpy buffers; out may be inp)."""
+    scheds = np.ascontiguousarray(scheds, dtype=SCHED_DTYPE)
+    reqs = np.ascontiguousarray(reqs, dtype=REQ_DTYPE)
+    if inp.dtype != np.uint8 or out.dtype != np.uint8 or inp.size != out.size:
+        raise ValueError("inp and out must be uint8 arrays of one size")
+    if not (inp.flags.c_contiguous and out.flags.c_contiguous and out.flags.writeable):
+        raise ValueError("inp and out must be contiguous, out writeable")
+    _check(lib().aes_host_batch(scheds.ctypes.data, scheds.size, inp.ctypes.data,
+                                out.ctypes.data, inp.size, reqs.ctypes.data, reqs.size,
+                                n_threads), "aes_host_batch")
 
 
 def tune_key(ctx: Context, reqs: np.ndarray, n_scheds: int) -> str:

@@ -12,8 +12,10 @@
 
 #include <algorithm>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "host_pool.h"
@@ -1476,6 +1478,46 @@ int aes_tune(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_
     if (best_out)
         *best_out = best;
     return AES_OK;
+}
+
+int aes_host_batch(const aes_schedule_t *scheds, uint32_t n_scheds, const uint8_t *in,
+                   uint8_t *out, uint64_t buf_bytes, const aes_req_t *reqs, uint64_t n_reqs,
+                   uint32_t n_threads) {
+    if (n_threads > 1024)
+        return AES_ERR_ARG;
+    int st = check_buffers(in, out, buf_bytes, n_reqs, scheds);
+    if (st)
+        return st;
+    if ((st = validate(reqs, n_reqs, n_scheds, buf_bytes)))
+        return st;
+    if (!n_reqs)
+        return AES_OK;
+    uint64_t nt = n_threads ? n_threads : std::thread::hardware_concurrency();
+    nt = std::max<uint64_t>(1, std::min<uint64_t>(nt, n_reqs));
+    // Requests are claimed one at a time (their sizes differ; k at a time
+    // only past 2^31 requests).  The error reported is the one of the
+    // lowest-numbered request that failed; the others still run.
+    const uint64_t k = (n_reqs + INT32_MAX - 1) / INT32_MAX;
+    std::mutex m;
+    uint64_t bad_i = UINT64_MAX;
+    int bad_code = AES_OK;
+    HostPool pool((int)nt - 1);
+    pool.run((int)((n_reqs + k - 1) / k), [&](int c) {
+        const uint64_t end = std::min<uint64_t>(n_reqs, ((uint64_t)c + 1) * k);
+        for (uint64_t i = (uint64_t)c * k; i < end; i++) {
+            const aes_req_t &r = reqs[i];
+            const int e = aes_host_route_crypt(&scheds[r.key_idx], r.op, r.iv, in + r.offset,
+                                               out + r.offset, r.length);
+            if (e) {
+                std::lock_guard<std::mutex> lk(m);
+                if (i < bad_i) {
+                    bad_i = i;
+                    bad_code = e;
+                }
+            }
+        }
+    });
+    return bad_code;
 }
 
 int aes_tune_key(const aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_scheds,
