@@ -96,7 +96,8 @@ def cpu_baseline(sample_pages: int):
             inp = wl.data()
             out = np.empty_like(inp)
             t0 = time.perf_counter()
-            threads = oracle.batch(inp, out, wl.reqs, wl.keys, wl.key_bits, n_threads=0)
+            threads = oracle.batch(inp, out, wl.reqs, wl.keys, wl.key_bits,
+                                   n_threads=len(os.sched_getaffinity(0)))
             secs += time.perf_counter() - t0
             total += wl.payload_bytes()
     # The size sweep's requests on one core of the oracle (plain scalar C).
