@@ -448,8 +448,11 @@ int aes_server_submit(aes_server_t *srv, uint32_t op, uint32_t key_slot, const u
  * without a callback) to out, oldest first. */
 int aes_server_poll(aes_server_t *srv, aes_done_t *out, uint32_t max, uint32_t *n_out);
 /* Blocks until `ticket` (posted without a callback) completes, then moves its
- * completion to *out (may be NULL).  Errors: AES_ERR_TIMEOUT, AES_ERR_ARG
- * (unknown ticket). */
+ * completion to *out (may be NULL).  The calling thread spins for up to
+ * 200 us (or timeout_ns, if shorter) before it sleeps, so a short request
+ * does not pay an operating-system wake-up; the server's completion thread
+ * likewise spins for 200 us after its last request before it sleeps.
+ * Errors: AES_ERR_TIMEOUT, AES_ERR_ARG (unknown ticket). */
 int aes_server_wait(aes_server_t *srv, uint64_t ticket, uint64_t timeout_ns, aes_done_t *out);
 /* Open-loop replay of a request trace: request i (offset into both bases,
  * length, key slot in key_idx, op, iv) is posted at arrival_s[i] seconds

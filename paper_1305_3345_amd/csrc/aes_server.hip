@@ -478,7 +478,18 @@ struct aes_server {
     aes_server_stats_t stats{};
     std::thread poller;
     std::atomic<bool> quit{false};
+    // Change counters read without mu: submits (the completion thread spins
+    // on it before sleeping) and completion rounds (aes_server_wait spins on
+    // it before sleeping).
+    std::atomic<uint64_t> n_submits{0};
+    std::atomic<uint64_t> n_finish_rounds{0};
 };
+
+// Spin budgets before a thread sleeps on a condition variable: a wake-up
+// through the OS costs tens of microseconds, more than a request's round
+// trip through the persistent kernel.
+constexpr uint64_t POLLER_SPIN_NS = 200000;  // the completion thread, after its last request
+constexpr uint64_t WAIT_SPIN_NS = 200000;    // aes_server_wait
 
 namespace {
 
@@ -614,8 +625,10 @@ void poll_loop(aes_server *s) {
                 }
             }
         }
-        if (progressed)
+        if (progressed) {
+            s->n_finish_rounds.fetch_add(1, std::memory_order_release);
             s->cv.notify_all();
+        }
         for (auto &c : cbs)
             c.first.cb(&c.second, c.first.user);
         cbs.clear();
@@ -624,9 +637,24 @@ void poll_loop(aes_server *s) {
                 for (int k = 0; k < 16; k++)
                     cpu_relax();
             } else {
-                // Idle: sleep until a submit (or shutdown) rather than for a
-                // fixed time, so that the first completion after an idle
-                // period is seen as soon as it lands.
+                // Idle: spin a little for the next submit (back-to-back
+                // callers then never wait for this thread to wake), then
+                // sleep until a submit (or shutdown) rather than for a fixed
+                // time, so that the first completion after an idle period is
+                // seen as soon as it lands.  A submit between the check
+                // above and the spin is caught by the wait's predicate.
+                const uint64_t seen = s->n_submits.load(std::memory_order_acquire);
+                const uint64_t until = host_ns() + POLLER_SPIN_NS;
+                bool woke = false;
+                while (!s->quit.load(std::memory_order_relaxed) && host_ns() < until) {
+                    if (s->n_submits.load(std::memory_order_acquire) != seen) {
+                        woke = true;
+                        break;
+                    }
+                    cpu_relax();
+                }
+                if (woke)
+                    continue;
                 std::unique_lock<std::mutex> lk(s->mu);
                 s->work_cv.wait_for(lk, std::chrono::milliseconds(5), [s] {
                     return !s->live.empty() || s->quit.load(std::memory_order_acquire);
@@ -779,6 +807,7 @@ int submit_locked(aes_server *s, uint32_t op, uint32_t key_slot, const uint8_t *
     s->inflight_bytes += length;
     s->inflight_units[queue] += units;
     s->live.push_back(ticket);
+    s->n_submits.fetch_add(1, std::memory_order_release);
     s->work_cv.notify_one();  // the completion thread may be idle
     s->stats.submitted++;
     if (ticket_out)
@@ -1056,6 +1085,7 @@ int aes_server_wait(aes_server_t *s, uint64_t ticket, uint64_t timeout_ns, aes_d
         return AES_ERR_ARG;
     std::unique_lock<std::mutex> lk(s->mu);
     const auto deadline = std::chrono::steady_clock::now() + std::chrono::nanoseconds(timeout_ns);
+    const uint64_t spin_until = host_ns() + std::min<uint64_t>(WAIT_SPIN_NS, timeout_ns);
     for (;;) {
         auto it = s->finished.find(ticket);
         if (it != s->finished.end()) {
@@ -1067,6 +1097,17 @@ int aes_server_wait(aes_server_t *s, uint64_t ticket, uint64_t timeout_ns, aes_d
         const SlotInfo &si = s->slots[ticket & s->mask];
         if (ticket >= s->next_ticket || !si.busy || si.ticket != ticket || si.cb)
             return AES_ERR_ARG;
+        // Spin first (without mu) until the completion thread finishes a
+        // round or the spin budget ends; then sleep on cv.
+        const uint64_t seen = s->n_finish_rounds.load(std::memory_order_acquire);
+        if (host_ns() < spin_until) {
+            lk.unlock();
+            while (s->n_finish_rounds.load(std::memory_order_acquire) == seen &&
+                   host_ns() < spin_until)
+                cpu_relax();
+            lk.lock();
+            continue;
+        }
         if (s->cv.wait_until(lk, deadline) == std::cv_status::timeout &&
             s->finished.find(ticket) == s->finished.end())
             return AES_ERR_TIMEOUT;
