@@ -517,8 +517,8 @@ int aes_host_route_crypt(const aes_schedule_t *sched, uint32_t op, const uint8_t
 /* A whole batch on the host route: the requests, buffer rules and results of
  * aes_batch, with host-memory schedules (n_scheds records) and host-memory
  * in/out buffers of buf_bytes each (in == out, or disjoint), run by
- * n_threads host threads (0 = all hardware threads; the calling thread is
- * one of them), each taking the next request.  A CPU baseline for the GPU
+ * n_threads host threads (0 = as many as the CPUs this process may run on;
+ * the calling thread is one of them), each taking the next request.  A CPU baseline for the GPU
  * forms and a CPU path for callers without a GPU; not the oracle.  Returns
  * when every request is done.  Errors: those of aes_batch's validation
  * (nothing runs), AES_ERR_ARG for n_threads > 1024; then, if requests failed

@@ -7,6 +7,7 @@
 // the unit table to the device through pinned staging and launches the round
 // kernels on the caller's stream.
 #include <hip/hip_runtime.h>
+#include <sched.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -1492,7 +1493,12 @@ int aes_host_batch(const aes_schedule_t *scheds, uint32_t n_scheds, const uint8_
         return st;
     if (!n_reqs)
         return AES_OK;
-    uint64_t nt = n_threads ? n_threads : std::thread::hardware_concurrency();
+    uint64_t nt = n_threads;
+    if (!nt) {  // the CPUs this process may run on (a machine may have more)
+        cpu_set_t set;
+        nt = sched_getaffinity(0, sizeof(set), &set) == 0 ? (uint64_t)CPU_COUNT(&set)
+                                                          : std::thread::hardware_concurrency();
+    }
     nt = std::max<uint64_t>(1, std::min<uint64_t>(nt, n_reqs));
     // Requests are claimed one at a time (their sizes differ; k at a time
     // only past 2^31 requests).  The error reported is the one of the
