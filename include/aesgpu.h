@@ -305,7 +305,8 @@ int aes_tune(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_
              uint64_t buf_bytes, const aes_schedule_t *d_scheds, const uint8_t *d_in,
              uint8_t *d_out, uint32_t iters, aes_launch_config_t *best);
 
-/* The tune cache's signature of a batch, as a NUL-terminated string in buf
+/* The tune cache's signature of a batch (the batched service of paper
+ * sections 2 and 3.3 is tuned per batch shape), as a NUL-terminated string in buf
  * (cap bytes): the device architecture and compute-unit count of ctx ("host"
  * and 0 for a host-only context), and size classes 2^k = floor(log2) ("-" for
  * zero) of the request count, of the requests per op (CBC-enc, CBC-dec,
@@ -514,7 +515,9 @@ int aes_server_calibrate(aes_server_t *srv, uint32_t key_slot, uint64_t out[5]);
 int aes_host_route_crypt(const aes_schedule_t *sched, uint32_t op, const uint8_t *iv,
                          const uint8_t *src, uint8_t *dst, uint64_t length);
 
-/* A whole batch on the host route: the requests, buffer rules and results of
+/* A whole batch on the host route (paper section 3.3 sets the GPU service
+ * against AES on the CPU; section 4 proposes running work the GPU would do
+ * no faster on the CPU): the requests, buffer rules and results of
  * aes_batch, with host-memory schedules (n_scheds records) and host-memory
  * in/out buffers of buf_bytes each (in == out, or disjoint), run by
  * n_threads host threads (0 = as many as the CPUs this process may run on;
