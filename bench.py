@@ -109,6 +109,7 @@ def cpu_baseline(sample_pages: int):
         oracle.mode(oracle.OP_ECB_ENC, keys[0][:16], 128, None, data[:n])
         e2[str(n)] = round((time.perf_counter() - t0) * 1e6, 1)
     return {"value": round(total / secs / 1e9, 4), "unit": "GB/s", "cores": threads,
+            "host_cpus": os.cpu_count(), "cpus_allowed": len(os.sched_getaffinity(0)),
             "kind": "oracle",
             "sample": f"first {sample_pages} pages of each of the 4 runs of a step "
                       f"({total >> 20} MiB), same keys/IVs/bytes, {secs:.1f} s",
