@@ -293,3 +293,62 @@ def test_replay_poisson_trace(ctx, engine):
     for r in tr.reqs[::5]:
         o, n = int(r["offset"]), int(r["length"])
         assert first_mismatch(got[o:o + n], oracle_request(wl, r, inp[o:o + n])) is None
+
+
+def expected_units(op, length, tile=4096, cap=128):
+    """Work units of one request in the persistent engine: one per tile, or
+    units of ceil(tiles / cap) tiles when it has more than cap tiles; one
+    chain for CBC encryption."""
+    if op == workloads.OP_CBC_ENC:
+        return 1
+    tiles = -(-length // tile)
+    per_unit = -(-tiles // cap) if tiles > cap else 1
+    return -(-length // (tile * per_unit))
+
+
+@pytest.mark.parametrize("inplace", [False, True])
+def test_large_requests_multi_tile_units(ctx, inplace):
+    """Requests of more than 128 tiles through the persistent engine, which
+    cuts them into about 128 units of several tiles each: every op, ragged CTR
+    tails, a CTR counter that wraps mod 2^64 inside the request (across a unit
+    boundary), sizes from 520 KiB to just under the 4 MiB request limit, each
+    equal to the oracle byte for byte (in place as well)."""
+    a = ag()
+    print(f"\n[gpu] persistent engine, large requests, in place={inplace}", flush=True)
+    sizes = [520 << 10, 1 << 20, (3 << 20) + 4096, (4 << 20) - 16]
+    ops = [0, 1, 2, 3, 4]  # CBC-enc, CBC-dec, CTR, ECB-enc, ECB-dec
+    n = len(sizes) * len(ops)
+    reqs = np.zeros(n, workloads.REQ_DTYPE)
+    for i in range(n):
+        reqs["op"][i] = ops[i % len(ops)]
+        ln = sizes[i // len(ops)]
+        if reqs["op"][i] == workloads.OP_CTR:
+            ln -= 5 + i  # ragged tail
+        reqs["length"][i] = ln
+    reqs["offset"][1:] = np.cumsum((reqs["length"] + 15) // 16 * 16 + 48)[:-1]
+    reqs["key_idx"] = np.arange(n) % 4
+    reqs["iv"] = gen.bytes_(9, gen.STREAM_IVS, 16 * n).reshape(n, 16)
+    # A CTR request whose counter wraps 1,000 blocks in (inside its second unit).
+    wrap = [i for i in range(n) if reqs["op"][i] == workloads.OP_CTR][1]
+    reqs["iv"][wrap, 8:] = np.frombuffer(((1 << 64) - 1000).to_bytes(8, "big"), np.uint8)
+    keys, kb = workloads.make_keys(9, 4, [128, 256, 192, 128])
+    buf = int(reqs["offset"][-1] + reqs["length"][-1] + 64)
+    wl = workloads.Workload("serve_large", reqs, keys, kb, buf, 9)
+    src = wl.data()
+    d_in = torch.from_numpy(src.copy()).cuda()
+    d_out = d_in if inplace else torch.zeros_like(d_in)
+    with server(ctx, wl, mode=a.AES_SERVE_PERSISTENT) as s:
+        for r in wl.reqs:
+            t = submit_retry(s, r, d_in.data_ptr() + int(r["offset"]),
+                             d_out.data_ptr() + int(r["offset"]))
+            done = s.wait(t)
+            assert done["status"] == 0
+            assert done["units"] == expected_units(int(r["op"]), int(r["length"]))
+        st = s.stats()
+    sync()
+    got = d_out.cpu().numpy()
+    for r in wl.reqs:
+        o, ln = int(r["offset"]), int(r["length"])
+        msg = first_mismatch(got[o:o + ln], oracle_request(wl, r, src[o:o + ln]))
+        assert msg is None, f"op {int(r['op'])} length {ln}: {msg}"
+    assert st["host_routed"] == 0
