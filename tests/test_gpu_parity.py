@@ -1,9 +1,11 @@
 """GPU parity: the HIP path through the C ABI against the CPU oracle, byte for
 byte (AES is a permutation, so the tolerance is zero bytes).
 
-Sizes span several workgroups and waves and a ragged tail; full-size shapes
-are checked on sampled requests, which the oracle computes one by one.
+Sizes span several workgroups and waves and a ragged tail; the benchmark's
+full-size shape is checked on every page.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -172,10 +174,10 @@ def test_bad_schedule_leaves_output_untouched(ctx):
 
 
 @pytest.mark.parametrize("op,bits", [(workloads.OP_CTR, 128), (workloads.OP_CBC_DEC, 256)])
-def test_config2_full_size_sampled(ctx, op, bits):
+def test_config2_full_size(ctx, op, bits):
     """Full config-2 size (65,536 pages, 256 MiB) in the benchmark's launch
-    form; 300 sampled pages plus the first and last are checked against the
-    oracle page by page, and the whole buffer must round-trip."""
+    form: every page against the oracle (its threaded batch over the whole
+    buffer), and the whole buffer must round-trip."""
     print(f"[gpu] config 2 full size op={op} bits={bits}", flush=True)
     a = ag()
     wl = workloads.config2(op, bits)
@@ -187,16 +189,10 @@ def test_config2_full_size_sampled(ctx, op, bits):
     plan.launch(d_s, d_in, d_out)
     torch.cuda.synchronize()
     got = d_out.cpu().numpy()
-    rng = np.random.default_rng(11)
-    sample = np.unique(np.concatenate([[0, wl.reqs.size - 1],
-                                       rng.choice(wl.reqs.size, 300, replace=False)]))
-    for p in sample:
-        r = wl.reqs[p]
-        o, n = int(r["offset"]), int(r["length"])
-        kb = int(wl.key_bits[r["key_idx"]])
-        want = oracle.mode(int(r["op"]), wl.keys[r["key_idx"]][: kb // 8], kb, r["iv"],
-                           inp[o:o + n])
-        check(got[o:o + n], want, f"page {p}")
+    want = np.empty_like(inp)
+    oracle.batch(inp, want, wl.reqs, wl.keys, wl.key_bits,
+                 n_threads=len(os.sched_getaffinity(0)))
+    check(got, want, "all 65,536 pages")
     # property over the whole buffer: the inverse operation restores the input
     back = torch.empty_like(d_in)
     inv = wl.reqs.copy()
