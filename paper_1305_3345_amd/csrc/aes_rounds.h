@@ -730,6 +730,29 @@ __device__ __forceinline__ uint32_t quad_next(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, sel, 0xF, 0xF, false);
 }
 
+// A round of the quad form.  Column j of the round's output takes row r from
+// column j + r (ShiftRows), so lane j needs Te_r of byte r of lane (j + r)'s
+// column.  Each lane looks up the four bytes of its own column and the quad
+// exchanges the looked-up words afterwards: the exchange then reads values
+// returned by LDS, not ones a VALU op has just written, and the lookups do not
+// wait for it.
+__device__ __forceinline__ uint32_t quad_round_col(const uint32_t *lds, uint32_t st, uint32_t k,
+                                                   uint32_t L0) {
+    const uint32_t a0 = tlook<0, 0>(lds, st, L0);
+    const uint32_t a1 = tlook<1, 1>(lds, st, L0);
+    const uint32_t a2 = tlook<2, 2>(lds, st, L0);
+    const uint32_t a3 = tlook<3, 3>(lds, st, L0);
+    return xor3(xor3(a0, quad_next<1>(a1), k), quad_next<2>(a2), quad_next<3>(a3));
+}
+
+// The last round's SubBytes/ShiftRows column in the quad form (byte r of
+// column j is S of byte r of lane (j + r)'s column), exchanged after lookup.
+__device__ __forceinline__ uint32_t quad_sub_col(const uint32_t *lds, uint32_t st, uint32_t L0) {
+    return pick_diag(tlook<0, 3>(lds, st, L0), quad_next<1>(tlook<1, 0>(lds, st, L0)),
+                     quad_next<2>(tlook<2, 1>(lds, st, L0)),
+                     quad_next<3>(tlook<3, 2>(lds, st, L0)));
+}
+
 // Runs a quad's chain.  Lanes of a quad share one chain (un, ek, nr); quads
 // of a wave may have different chains, keys and key sizes: rounds run up to
 // MAXNR, a quad with fewer rounds sits out the extra ones.
@@ -764,11 +787,9 @@ __device__ __forceinline__ void chain_quad_run(const uint32_t *lds, uint32_t L0,
 #pragma unroll
                 for (int r = 1; r < MAXNR; r++) {
                     if (r < 10 || (uint32_t)r < nr)
-                        st = round_col(lds, st, quad_next<1>(st), quad_next<2>(st),
-                                       quad_next<3>(st), rk[r], L0);
+                        st = quad_round_col(lds, st, rk[r], L0);
                 }
-                prev = sub_col(lds, st, quad_next<1>(st), quad_next<2>(st), quad_next<3>(st), L0) ^
-                       rkl;
+                prev = quad_sub_col(lds, st, L0) ^ rkl;
                 dst[4 * (b + j)] = prev;
             }
         }
