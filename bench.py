@@ -460,9 +460,9 @@ def bench_e2(dev, reps=15):
                     persist.append((time.perf_counter() - t0) * 1e6)
             row["gpu_persistent_us"] = round(med(persist), 1)
     # The paper's E1: an (almost) empty service call -- one 16-byte block --
-    # through persistent kernels of 1,024 and 2,048 threads (two and four
-    # 512-thread workgroups, the smallest grids the two table sets allow) and
-    # the default grid, against one normal kernel launch.
+    # through persistent kernels of 512, 1,024 and 2,048 threads (one, two and
+    # four 512-thread workgroups; one workgroup holds the encryption tables
+    # only) and the default grid, against one normal kernel launch.
     req = np.zeros(1, aesgpu.REQ_DTYPE)
     req["length"] = 16
     req["op"] = aesgpu.AES_OP_ECB_ENC
@@ -474,7 +474,7 @@ def bench_e2(dev, reps=15):
         if i >= 2:
             launch.append((time.perf_counter() - t0) * 1e6)
     e1 = {"launch_us": round(med(launch), 1), "persistent_us": {}}
-    for nwg in (2, 4, 0):
+    for nwg in (1, 2, 4, 0):
         with aesgpu.Server(ctx, key_slots=1, n_workgroups=nwg) as srv:
             srv.set_key(0, sched[0])
             rt = []

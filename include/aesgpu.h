@@ -190,8 +190,8 @@ typedef struct aes_plan aes_plan_t;
  *      ECB -- zero.
  * CTR, ECB and CBC-decryption requests become tiles of the context's tile
  * size (4096 bytes by default); each CBC-encryption request is one unit (a
- * serial chain), and chains are grouped by key, longest first within a
- * key. */
+ * serial chain), and chains are ordered longest first, chains of equal
+ * length by key index. */
 typedef struct aes_unit {
     uint64_t offset;
     uint32_t nbytes;
@@ -224,8 +224,8 @@ int aes_plan_launch(aes_plan_t *plan, const aes_schedule_t *d_scheds, const uint
                     uint8_t *d_out, void *stream);
 int aes_plan_info(const aes_plan_t *plan, aes_plan_info_t *info);
 /* Copies up to max unit records (CBC- and ECB-decrypt tiles in request order,
- * then CTR tiles, then ECB-encrypt tiles, then chains grouped by key, longest
- * first within a key) to out and sets *n_out to the plan's total unit count.
+ * then CTR tiles, then ECB-encrypt tiles, then chains longest first, those of
+ * equal length by key index) to out and sets *n_out to the plan's total unit count.
  * CTR and ECB-encrypt tiles are in request order, or, when the context's CTR
  * variant was AES_CTR_BITSLICE at planning time, grouped by key with request
  * order kept within a key. */
@@ -390,8 +390,14 @@ typedef struct aes_server_config {
     uint32_t mode;              /* AES_SERVE_PERSISTENT (default) or AES_SERVE_PER_LAUNCH */
     uint32_t ring_slots;        /* power of two, 64..65536 (default 4096) */
     uint32_t key_slots;         /* resident key schedules, 1..65536 (default 256) */
-    uint32_t n_workgroups;      /* persistent grid; 0 = compute units minus 16 */
-    uint32_t dec_workgroups;    /* of those, workgroups holding decryption tables; 0 = half */
+    uint32_t n_workgroups;      /* persistent grid of 512-thread workgroups, each holding a
+                                   whole compute unit's LDS; 0 = compute units minus 16; at
+                                   most the workgroups the device holds at once (the compute
+                                   units), else AES_ERR_ARG.  1 = one workgroup with the
+                                   encryption tables only (CTR, ECB and CBC encryption in the
+                                   kernel; decryption requests take a normal launch) */
+    uint32_t dec_workgroups;    /* of those, workgroups holding decryption tables; 0 = half;
+                                   1 .. n_workgroups - 1, and 0 when n_workgroups is 1 */
     uint32_t n_streams;         /* per-launch engine: stream pool (default 8) */
     uint32_t queue_units;       /* persistent engine: device queue capacity in work units per
                                    table set, power of two (default 65536) */
@@ -430,18 +436,24 @@ typedef struct aes_server_stats {
     uint64_t host_routed; /* requests run on the host route (size-based dispatch) */
 } aes_server_stats_t;
 
-/* cfg may be NULL (defaults).  Errors: AES_ERR_ARG, AES_ERR_DEVICE, AES_ERR_NOMEM. */
+/* cfg may be NULL (defaults).  The persistent kernel is launched by the first
+ * submit, not here.  While it runs, its workgroups occupy n_workgroups compute
+ * units; kernels of other calls on the device share the rest.
+ * Errors: AES_ERR_ARG, AES_ERR_DEVICE, AES_ERR_NOMEM. */
 int aes_server_create(aes_ctx_t *ctx, const aes_server_config_t *cfg, aes_server_t **out);
 /* Copies a schedule into resident slot `slot` (synchronously).  Allowed while
  * nothing is in flight (else AES_ERR_STATE); a running persistent kernel is
- * stopped first and relaunched by the next submit. */
+ * stopped first (AES_ERR_TIMEOUT if it does not exit within 10 s) and
+ * relaunched by the next submit. */
 int aes_server_set_key(aes_server_t *srv, uint32_t slot, const aes_schedule_t *host_sched);
 /* Posts one request (paper section 3.2: buffers, a service request, an
  * optional completion callback).  op and iv as in aes_req_t (iv may be NULL
  * for ECB); length > 0, < 2^32, a multiple of 16 for CBC and ECB.  Sets
  * *ticket.  Errors: AES_ERR_ARG, AES_ERR_LENGTH, AES_ERR_RANGE (key slot, or
  * a range that starts inside a buffer from aes_server_host_alloc and runs
- * past its end), AES_ERR_OVERLAP, AES_ERR_AGAIN (admission), AES_ERR_DEVICE. */
+ * past its end), AES_ERR_STATE (the key slot was never loaded with
+ * aes_server_set_key), AES_ERR_OVERLAP, AES_ERR_AGAIN (admission),
+ * AES_ERR_DEVICE. */
 int aes_server_submit(aes_server_t *srv, uint32_t op, uint32_t key_slot, const uint8_t iv[16],
                       const uint8_t *d_src, uint8_t *d_dst, uint64_t length, aes_done_cb cb,
                       void *user, uint64_t *ticket);
@@ -532,8 +544,12 @@ int aes_host_route_crypt(const aes_schedule_t *sched, uint32_t op, const uint8_t
 int aes_host_batch(const aes_schedule_t *scheds, uint32_t n_scheds, const uint8_t *in,
                    uint8_t *out, uint64_t buf_bytes, const aes_req_t *reqs, uint64_t n_reqs,
                    uint32_t n_threads);
-/* Waits (up to 10 s) for in-flight requests, stops the kernel and frees
- * everything.  Returns AES_ERR_TIMEOUT if requests were still in flight. */
+/* Waits (up to 10 s) for in-flight requests, stops the persistent kernel
+ * (waiting up to 10 s for it to exit) and frees the server; the handle is
+ * invalid afterwards in every case.  Returns AES_ERR_TIMEOUT if requests were
+ * still in flight or the kernel did not exit; in the second case the memory
+ * and stream that kernel may still use are left allocated (leaked), not freed
+ * under it. */
 int aes_server_destroy(aes_server_t *srv);
 
 #ifdef __cplusplus

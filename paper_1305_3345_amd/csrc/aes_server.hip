@@ -45,6 +45,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -105,9 +106,8 @@ struct ServeQueue {
 struct ServeCtl {
     uint32_t stop;  // host -> device
     uint32_t pad0[31];
-    uint64_t consumed;   // device -> host: ring positions taken
-    uint64_t heartbeat;  // device -> host: dispatcher polls
-    uint64_t pad1[14];
+    uint64_t consumed;  // device -> host: ring positions taken
+    uint64_t pad1[15];
 };
 
 struct ServeArgs {
@@ -157,7 +157,6 @@ __device__ void dispatch_loop(const ServeArgs &a) {
     uint64_t tail[2] = {__hip_atomic_load(&a.q[0].tail, __ATOMIC_RELAXED, AGT),
                         __hip_atomic_load(&a.q[1].tail, __ATOMIC_RELAXED, AGT)};
     uint64_t last_work = now_ticks();
-    uint32_t polls = 0;
     for (;;) {
         const uint64_t t = next + lane;
         ServeDesc *d = a.ring + (t & a.ring_mask);
@@ -167,8 +166,6 @@ __device__ void dispatch_loop(const ServeArgs &a) {
         if (n_ready)
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
         if (n_ready == 0) {
-            if ((++polls & 63u) == 0 && lane == 0)
-                __hip_atomic_store(&a.ctl->heartbeat, (uint64_t)polls, __ATOMIC_RELAXED, SYS);
             const uint32_t stop = __hip_atomic_load(&a.ctl->stop, __ATOMIC_RELAXED, SYS);
             if (stop || now_ticks() - last_work > a.idle_ticks)
                 break;
@@ -216,15 +213,15 @@ __device__ void dispatch_loop(const ServeArgs &a) {
                 __hip_atomic_store(&a.done[slot].units, k_units, __ATOMIC_RELAXED, SYS);
             // The host validates every request; these checks keep a bad
             // descriptor from reaching the kernels.
+            const int qi = op == AES_OP_CBC_DEC || op == AES_OP_ECB_DEC ? 1 : 0;
             const bool ok = op <= AES_OP_ECB_DEC && key < a.n_keys && r_len > 0 &&
                             r_len <= a.max_bytes && (op == AES_OP_CTR || (r_len & 15u) == 0) &&
-                            r_src && r_dst;
+                            r_src && r_dst && (qi == 0 || a.n_dec_wg > 0);
             if (!ok) {
                 if (lane == 0)
                     complete(a, slot, pos, AES_ERR_ARG);
                 continue;
             }
-            const int qi = op == AES_OP_CBC_DEC || op == AES_OP_ECB_DEC ? 1 : 0;
             const uint32_t k = k_units;
             // No wait for room: the host admits at most queue_units units
             // per queue in flight, so published units are never overwritten
@@ -386,15 +383,21 @@ __global__ void k_serve_reset(ServeQueue *q, uint32_t *closed) {
     }
 }
 
+// The grid: workgroup 0 (encryption tables) carries the dispatcher on its
+// first wave, so that the one wave every other wave waits for is the first
+// placed; the last n_dec_wg workgroups hold the decryption tables (none in a
+// one-workgroup grid, whose decryption requests the host sends to a normal
+// launch).  Every workgroup takes a whole compute unit's LDS, and the host
+// never launches more workgroups than the device holds at once.
 __global__ __launch_bounds__(512) void k_serve(ServeArgs a) {
     __shared__ uint32_t lds[LDS_DEC_WORDS];
-    const bool dec = blockIdx.x < a.n_dec_wg;
+    const bool dec = blockIdx.x >= gridDim.x - a.n_dec_wg;
     if (dec)
         fill_tables<true>(lds, a.timg);
     else
         fill_tables<false>(lds, a.timg);
     __syncthreads();
-    if (blockIdx.x == gridDim.x - 1 && (threadIdx.x >> 6) == 0) {
+    if (blockIdx.x == 0 && (threadIdx.x >> 6) == 0) {
         dispatch_loop(a);
         return;
     }
@@ -461,7 +464,8 @@ struct aes_server {
     // device memory
     aes_schedule_t *keys_d = nullptr;
     std::vector<aes_schedule_t> keys_h;  // host copies for the host route
-    std::vector<uint8_t> key_set;
+    // Slots loaded by aes_server_set_key (read without mu by submits).
+    std::unique_ptr<std::atomic<uint8_t>[]> key_set;
     uint64_t crossover[5] = {0, 0, 0, 0, 0};  // by op; 0 = never the host route
     ServeUnit *qunits_d[2] = {nullptr, nullptr};
     ServeQueue *q_d = nullptr;
@@ -504,6 +508,11 @@ struct aes_server {
 // trip through the persistent kernel.
 constexpr uint64_t POLLER_SPIN_NS = 200000;  // the completion thread, after its last request
 constexpr uint64_t WAIT_SPIN_NS = 200000;    // aes_server_wait
+// How long stop_persistent waits for the kernel after raising the stop flag.
+// Once the dispatcher sees the flag it publishes nothing more, and the
+// workers finish the units already published (at most queue_units units of
+// at most 4 MiB in all), which takes milliseconds.
+constexpr uint64_t STOP_WAIT_NS = 10000000000ull;
 
 namespace {
 
@@ -544,12 +553,21 @@ int launch_persistent(aes_server *s) {
     return AES_OK;
 }
 
-// Asks the persistent kernel to exit and waits for it (caller holds mu).
+// Asks the persistent kernel to exit and waits for it, for at most
+// STOP_WAIT_NS (caller holds mu).  AES_ERR_TIMEOUT: the kernel is still
+// running (the stop flag stays raised and the server still counts it as
+// running).
 int stop_persistent(aes_server *s) {
     if (!s->running)
         return AES_OK;
     __atomic_store_n(&s->ctl->stop, 1u, __ATOMIC_RELEASE);
-    hipError_t e = hipStreamSynchronize(s->kstream);
+    const uint64_t deadline = host_ns() + STOP_WAIT_NS;
+    hipError_t e;
+    while ((e = hipStreamQuery(s->kstream)) == hipErrorNotReady) {
+        if (host_ns() > deadline)
+            return AES_ERR_TIMEOUT;
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
     s->running = false;
     __atomic_store_n(&s->ctl->stop, 0u, __ATOMIC_RELEASE);
     return e == hipSuccess ? AES_OK : hip_fail_status(e);
@@ -687,6 +705,10 @@ int check_request(aes_server *s, uint32_t op, uint32_t key_slot, const uint8_t *
         return AES_ERR_LENGTH;
     if (key_slot >= s->cfg.key_slots)
         return AES_ERR_RANGE;
+    // A slot never loaded holds no schedule: the kernels would skip the
+    // request and leave its output unwritten.
+    if (!s->key_set[key_slot].load(std::memory_order_acquire))
+        return AES_ERR_STATE;
     if (src != dst) {
         const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
         if (a < b + length && b < a + length)
@@ -725,8 +747,11 @@ int submit_locked(aes_server *s, uint32_t op, uint32_t key_slot, const uint8_t *
     uint8_t *dst_d = dst_host ? hd->d + (dst - hd->h) : dst;
     const uint64_t ticket = s->next_ticket;
     const uint32_t slot = (uint32_t)(ticket & s->mask);
+    const bool dec_op = op == AES_OP_CBC_DEC || op == AES_OP_ECB_DEC;
+    // A persistent grid without decryption workgroups sends decryption to a
+    // normal launch, as it does requests above max_request_bytes.
     const bool by_launch = s->cfg.mode == AES_SERVE_PER_LAUNCH ||
-                           length > s->cfg.max_request_bytes;
+                           length > s->cfg.max_request_bytes || (dec_op && !s->n_dec_wg);
     const uint64_t ring_pos = s->ring_next;
     const uint32_t rslot = (uint32_t)(ring_pos & s->mask);
     if (s->slots[slot].busy || (!by_launch && s->ring_busy[rslot]) ||
@@ -736,7 +761,7 @@ int submit_locked(aes_server *s, uint32_t op, uint32_t key_slot, const uint8_t *
     }
     // Units this request adds to its device queue; the queue never holds
     // more than queue_units unconsumed units (see the dispatcher).
-    const int queue = op == AES_OP_CBC_DEC || op == AES_OP_ECB_DEC ? 1 : 0;
+    const int queue = dec_op ? 1 : 0;
     const uint32_t units =
         by_launch ? 0u : (op == AES_OP_CBC_ENC ? 1u : (uint32_t)((length + 4095) / 4096));
     if (s->inflight_units[queue] + units > s->cfg.queue_units) {
@@ -842,7 +867,7 @@ int try_host_route(aes_server *s, uint32_t op, uint32_t key_slot, const uint8_t 
     {
         std::lock_guard<std::mutex> lk(s->mu);
         const HostBuf *b;
-        if (length >= s->crossover[op] || !s->key_set[key_slot] ||
+        if (length >= s->crossover[op] || !s->key_set[key_slot].load(std::memory_order_relaxed) ||
             find_host(s, src, length, &b) != 1 || find_host(s, dst, length, &b) != 1)
             return 1;
         ticket = s->next_ticket;
@@ -881,7 +906,11 @@ int try_host_route(aes_server *s, uint32_t op, uint32_t key_slot, const uint8_t 
     return AES_OK;
 }
 
-void free_server(aes_server *s) {
+// Frees a server.  kernel_alive: its persistent kernel did not stop, so the
+// memory and streams that kernel may still touch (ring, completions,
+// control block, queues, key slots, payload buffers, its stream) are left
+// allocated rather than freed under it; the host-side state is freed.
+void free_server(aes_server *s, bool kernel_alive = false) {
     if (s->poller.joinable()) {
         {
             std::lock_guard<std::mutex> lk(s->mu);  // no lost wakeup of the idle wait
@@ -891,6 +920,10 @@ void free_server(aes_server *s) {
         s->poller.join();
     }
     (void)hipSetDevice(s->device);
+    if (kernel_alive) {
+        delete s;
+        return;
+    }
     for (hipEvent_t e : s->events)
         (void)hipEventDestroy(e);
     for (hipStream_t st : s->streams)
@@ -966,17 +999,33 @@ int aes_server_create(aes_ctx_t *ctx, const aes_server_config_t *cfg_in, aes_ser
     s->device = ci.device;
     s->mask = cfg.ring_slots - 1;
     s->timg_d = ci.d_timg;
-    int n_wg = cfg.n_workgroups ? (int)cfg.n_workgroups : ci.n_cu - 16;
-    if (n_wg < 2)
-        n_wg = 2;
-    int n_dec = cfg.dec_workgroups ? (int)cfg.dec_workgroups : n_wg / 2;
-    if (n_dec < 1 || n_dec > n_wg - 1) {
+    // Every workgroup of the persistent grid must be resident at once (the
+    // workers wait on the dispatcher's wave): at most the compute units times
+    // the workgroups of k_serve one compute unit holds (one: each takes a
+    // whole compute unit's LDS).  One workgroup holds the encryption tables
+    // only; from two on, dec_workgroups of them (default half) hold the
+    // decryption tables.
+    hipError_t e;
+    int per_cu = 0;
+    if ((e = hipSetDevice(s->device)) != hipSuccess ||
+        (e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, aesgpu::k_serve, 512, 0)) !=
+            hipSuccess) {
+        delete s;
+        return hip_fail_status(e);
+    }
+    const long max_wg = (long)ci.n_cu * per_cu;
+    long n_wg = cfg.n_workgroups ? (long)cfg.n_workgroups : (long)ci.n_cu - 16;
+    if (!cfg.n_workgroups && n_wg < 2)
+        n_wg = max_wg < 2 ? max_wg : 2;
+    long n_dec = n_wg == 1 ? 0 : (cfg.dec_workgroups ? (long)cfg.dec_workgroups : n_wg / 2);
+    if (cfg.mode == AES_SERVE_PERSISTENT &&
+        (n_wg < 1 || n_wg > max_wg || (n_wg == 1 && cfg.dec_workgroups) ||
+         (n_wg > 1 && (n_dec < 1 || n_dec > n_wg - 1)))) {
         delete s;
         return AES_ERR_ARG;
     }
     s->n_wg = (uint32_t)n_wg;
     s->n_dec_wg = (uint32_t)n_dec;
-    hipError_t e;
 #define SRV_TRY(expr)                                                                              \
     do {                                                                                           \
         if ((e = (expr)) != hipSuccess) {                                                          \
@@ -984,7 +1033,6 @@ int aes_server_create(aes_ctx_t *ctx, const aes_server_config_t *cfg_in, aes_ser
             return hip_fail_status(e);                                                             \
         }                                                                                          \
     } while (0)
-    SRV_TRY(hipSetDevice(s->device));
     const unsigned hflags = hipHostMallocMapped | hipHostMallocCoherent;
     SRV_TRY(hipHostMalloc((void **)&s->ring, sizeof(ServeDesc) * cfg.ring_slots, hflags));
     SRV_TRY(hipHostMalloc((void **)&s->done, sizeof(ServeDone) * cfg.ring_slots, hflags));
@@ -1024,7 +1072,13 @@ int aes_server_create(aes_ctx_t *ctx, const aes_server_config_t *cfg_in, aes_ser
     s->slots.resize(cfg.ring_slots);
     s->ring_busy.assign(cfg.ring_slots, 0);
     s->keys_h.assign(cfg.key_slots, aes_schedule_t());
-    s->key_set.assign(cfg.key_slots, 0);
+    s->key_set.reset(new (std::nothrow) std::atomic<uint8_t>[cfg.key_slots]);
+    if (!s->key_set) {
+        free_server(s);
+        return AES_ERR_NOMEM;
+    }
+    for (uint32_t i = 0; i < cfg.key_slots; i++)
+        s->key_set[i].store(0, std::memory_order_relaxed);
     s->live.reserve(cfg.ring_slots);
     try {
         s->poller = std::thread(poll_loop, s);
@@ -1054,7 +1108,7 @@ int aes_server_set_key(aes_server_t *s, uint32_t slot, const aes_schedule_t *hos
                        hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail_status(e);
     s->keys_h[slot] = *host_sched;
-    s->key_set[slot] = 1;
+    s->key_set[slot].store(1, std::memory_order_release);
     return AES_OK;
 }
 
@@ -1257,7 +1311,7 @@ int aes_server_calibrate(aes_server_t *s, uint32_t key_slot, uint64_t out[5]) {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->inflight)
             return AES_ERR_STATE;
-        if (!s->key_set[key_slot])
+        if (!s->key_set[key_slot].load(std::memory_order_relaxed))
             return AES_ERR_RANGE;
         sched = s->keys_h[key_slot];
         memcpy(saved, s->crossover, sizeof(saved));
@@ -1328,6 +1382,7 @@ int aes_server_destroy(aes_server_t *s) {
     if (!s)
         return AES_OK;
     int rc = AES_OK;
+    bool kernel_alive = false;
     {
         std::unique_lock<std::mutex> lk(s->mu);
         const auto deadline = std::chrono::steady_clock::now() + std::chrono::seconds(10);
@@ -1339,6 +1394,8 @@ int aes_server_destroy(aes_server_t *s) {
         }
         (void)hipSetDevice(s->device);
         int st = stop_persistent(s);
+        if (st == AES_ERR_TIMEOUT)
+            kernel_alive = true;
         if (st && !rc)
             rc = st;
         if (s->fbstream)
@@ -1346,7 +1403,7 @@ int aes_server_destroy(aes_server_t *s) {
         for (hipStream_t st2 : s->streams)
             (void)hipStreamSynchronize(st2);
     }
-    free_server(s);
+    free_server(s, kernel_alive);
     return rc;
 }
 

@@ -352,3 +352,107 @@ def test_large_requests_multi_tile_units(ctx, inplace):
         msg = first_mismatch(got[o:o + ln], oracle_request(wl, r, src[o:o + ln]))
         assert msg is None, f"op {int(r['op'])} length {ln}: {msg}"
     assert st["host_routed"] == 0
+
+
+def make_all_ops_trace(n, seed):
+    """n requests cycling through all five ops (CBC-enc, CBC-dec, CTR with a
+    ragged tail, ECB-enc, ECB-dec), 4..64 KiB, four 128/256-bit key slots."""
+    wl = make_trace(n, seed=seed, n_keys=4)
+    r = wl.reqs
+    r["op"] = np.arange(n) % 5
+    r["length"] = (r["length"] + 15) // 16 * 16
+    ctr = r["op"] == workloads.OP_CTR
+    r["length"][ctr] -= np.uint64(7)
+    r["offset"][1:] = np.cumsum((r["length"] + 15) // 16 * 16 + 64)[:-1]
+    wl.buf_bytes = int(r["offset"][-1] + r["length"][-1] + 64)
+    return wl
+
+
+@pytest.mark.parametrize("n_wg", [1, 2, 4])
+def test_small_persistent_grids(ctx, n_wg):
+    """The persistent engine at 512, 1,024 and 2,048 threads (one, two and
+    four 512-thread workgroups; section 3.1 of the paper measures its
+    Non-Stop Kernel at those sizes): every op against the oracle, alone and
+    in the mix.  One workgroup holds the encryption tables only, so its
+    decryption requests take a normal launch (counted as fallbacks); from
+    two workgroups on, every request runs in the persistent kernel."""
+    print(f"[gpu] persistent grid of {n_wg} workgroup(s)", flush=True)
+    wl = make_all_ops_trace(40, seed=41 + n_wg)
+    inp = wl.data()
+    d_in = torch.from_numpy(inp).cuda()
+    sync()
+    outs = {}
+    with server(ctx, wl, mode=0, n_workgroups=n_wg) as s:
+        for form in ("alone", "mix"):
+            d_out = torch.from_numpy(workloads.sentinel(inp.size)).cuda()
+            sync()
+            if form == "alone":
+                for r in wl.reqs:
+                    t = submit_retry(s, r, d_in.data_ptr() + int(r["offset"]),
+                                     d_out.data_ptr() + int(r["offset"]))
+                    assert s.wait(t)["status"] == 0
+            else:
+                ts = [submit_retry(s, r, d_in.data_ptr() + int(r["offset"]),
+                                   d_out.data_ptr() + int(r["offset"])) for r in wl.reqs]
+                for t in ts:
+                    assert s.wait(t)["status"] == 0
+            outs[form] = d_out.cpu().numpy()
+        st = s.stats()
+    n_dec = int(np.isin(wl.reqs["op"], [workloads.OP_CBC_DEC, 4]).sum())
+    assert st["fallbacks"] == (2 * n_dec if n_wg == 1 else 0)
+    assert st["kernel_launches"] >= 1
+    assert first_mismatch(outs["alone"], outs["mix"]) is None
+    for r in wl.reqs:
+        o, n = int(r["offset"]), int(r["length"])
+        msg = first_mismatch(outs["mix"][o:o + n], oracle_request(wl, r, inp[o:o + n]))
+        assert msg is None, f"op {int(r['op'])} at {o}: {msg}"
+
+
+def test_persistent_grid_limits(ctx):
+    """Grids the device cannot hold at once, and table splits that leave a
+    side without workgroups, are refused when the server is created (no
+    kernel is launched before the first submit)."""
+    print("[gpu] persistent grid limits", flush=True)
+    a = ag()
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    for cfg in ({"n_workgroups": n_cu + 1}, {"n_workgroups": 4 * n_cu},
+                {"n_workgroups": 1, "dec_workgroups": 1},
+                {"n_workgroups": 2, "dec_workgroups": 2},
+                {"n_workgroups": 8, "dec_workgroups": 8}):
+        with pytest.raises(a.AesError) as e:
+            a.Server(ctx, mode=0, **cfg)
+        assert e.value.status == a.AES_ERR_ARG, cfg
+    # the largest grid the device holds is accepted (and not launched here)
+    a.Server(ctx, mode=0, n_workgroups=n_cu).close()
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_unloaded_key_slot(ctx, engine):
+    """A key slot never loaded with aes_server_set_key is refused at submit
+    (AES_ERR_STATE) rather than reaching the kernels with an empty schedule;
+    loaded slots of the same server keep working."""
+    print(f"[gpu] unloaded key slot, engine={engine}", flush=True)
+    a = ag()
+    wl = make_trace(6, seed=44, n_keys=4)
+    inp = wl.data()
+    d_in = torch.from_numpy(inp).cuda()
+    d_out = torch.from_numpy(workloads.sentinel(inp.size)).cuda()
+    sync()
+    scheds = a.expand_keys(wl.keys, wl.key_bits)
+    with a.Server(ctx, mode=engine, key_slots=8) as s:
+        for i in range(4):
+            s.set_key(i, scheds[i])
+        for slot in (4, 7):
+            with pytest.raises(a.AesError) as e:
+                s.submit(workloads.OP_CTR, slot, bytes(16), d_in.data_ptr(), d_out.data_ptr(),
+                         4096)
+            assert e.value.status == a.AES_ERR_STATE
+        assert s.stats()["submitted"] == 0
+        ts = [submit_retry(s, r, d_in.data_ptr() + int(r["offset"]),
+                           d_out.data_ptr() + int(r["offset"])) for r in wl.reqs]
+        for t in ts:
+            assert s.wait(t)["status"] == 0
+        got = d_out.cpu().numpy()
+    for r in wl.reqs:
+        o, n = int(r["offset"]), int(r["length"])
+        assert first_mismatch(got[o:o + n], oracle_request(wl, r, inp[o:o + n])) is None
