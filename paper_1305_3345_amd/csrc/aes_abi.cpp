@@ -145,7 +145,7 @@ inline uint64_t be64(const uint8_t *p) {
 struct Planned {
     std::vector<Unit> dec;     // CBC- and ECB-decrypt tiles
     std::vector<Unit> ctr;     // CTR tiles, then ECB-encrypt tiles (the last n_ecb)
-    std::vector<Unit> chains;  // CBC-encrypt chains, by key, longest first within a key
+    std::vector<Unit> chains;  // CBC-encrypt chains, longest first, ties by key
     uint64_t payload = 0;
     uint64_t extent = 0;
     uint64_t dec_bytes = 0, ctr_bytes = 0, chain_bytes = 0;
@@ -276,13 +276,14 @@ int plan_units(const aes_req_t *reqs, uint64_t n, uint32_t tile_bytes, bool grou
         }
         p.n_ecb = p.ecb.size();
         p.ctr.insert(p.ctr.end(), p.ecb.begin(), p.ecb.end());
-        // Chains grouped by key, longest first within a key: a wave runs the
-        // largest round count among its chains for all of them, so chains
-        // that share a key (and so a key size) share waves; and longer
-        // chains start first.
+        // Chains longest first across the batch, so that when there are more
+        // chains than chain slots the longest start in the first pass and the
+        // batch's makespan is as short as the chains allow; chains of equal
+        // length are grouped by key (a wave runs the largest round count
+        // among its chains for all of them, so same-key chains share waves).
         std::stable_sort(p.chains.begin(), p.chains.end(), [](const Unit &a, const Unit &b) {
             const uint32_t ka = a.meta & META_KEY_MASK, kb = b.meta & META_KEY_MASK;
-            return ka != kb ? ka < kb : a.nbytes > b.nbytes;
+            return a.nbytes != b.nbytes ? a.nbytes > b.nbytes : ka < kb;
         });
     } catch (const std::bad_alloc &) {
         return AES_ERR_NOMEM;

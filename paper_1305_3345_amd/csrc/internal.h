@@ -56,7 +56,7 @@ struct ChainLaunch {
 struct MixedArgs {
     const Unit *dec;        // CBC-decrypt tiles
     const Unit *ctr;        // CTR tiles
-    const Unit *chains;     // CBC-encrypt chains, by key, longest first within a key
+    const Unit *chains;     // CBC-encrypt chains, longest first, ties by key
     const uint32_t *preds;  // NULL or 4 words per CBC-decrypt tile (in-place snapshots)
     const aes_schedule_t *sched;
     const uint32_t *timg;

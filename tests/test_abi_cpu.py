@@ -212,9 +212,10 @@ def _check_plan(ag, plan, reqs, tile, grouped=False):
     assert (np.diff((enc_ops == ag.AES_OP_ECB_ENC).astype(np.int64)) >= 0).all()
     ch = units[k + info["n_units_ctr"]:]
     ch_key = (ch["meta"] & 0xFFFFFF).astype(np.int64)
-    assert (np.diff(ch_key) >= 0).all()  # chains grouped by key ...
-    for key in np.unique(ch_key):  # ... longest first within a key
-        assert (np.diff(ch["nbytes"][ch_key == key].astype(np.int64)) <= 0).all()
+    ch_len = ch["nbytes"].astype(np.int64)
+    assert (np.diff(ch_len) <= 0).all()  # chains longest first ...
+    for ln in np.unique(ch_len):  # ... those of equal length by key
+        assert (np.diff(ch_key[ch_len == ln]) >= 0).all()
     # CTR tiles, then ECB-encrypt tiles: each group in request order, or
     # (grouped) by key with request order kept within a key
     enc = units[k:k + info["n_units_ctr"]]
@@ -283,6 +284,30 @@ def test_plan_unsorted_requests(ag, hctx):
     plan = ag.Plan(hctx, wl.reqs[perm], wl.keys.shape[0], wl.buf_bytes)
     _check_plan(ag, plan, wl.reqs[perm], 4096)
     plan.close()
+
+
+def test_plan_chains_longest_first_across_keys(ag, hctx):
+    """More CBC-encrypt chains than a launch starts in its first pass: the
+    longest chain comes first even under the highest key index and last in
+    request order, and chains of equal length follow key order (and request
+    order within a key)."""
+    n = 300
+    r = np.random.default_rng(7)
+    reqs = np.zeros(n, workloads.REQ_DTYPE)
+    reqs["length"] = r.choice([4096, 16384, 65536], n).astype(np.uint64)
+    reqs["length"][-1] = 1 << 20  # the longest chain: last request, highest key
+    reqs["offset"][1:] = np.cumsum(reqs["length"])[:-1]
+    reqs["key_idx"] = r.integers(0, 63, n)
+    reqs["key_idx"][-1] = 63
+    reqs["op"] = workloads.OP_CBC_ENC
+    reqs["iv"] = gen.bytes_(0, gen.STREAM_IVS, 16 * n).reshape(n, 16)
+    plan = ag.Plan(hctx, reqs, 64, int(reqs["offset"][-1] + reqs["length"][-1]))
+    _check_plan(ag, plan, reqs, 4096)
+    ch = plan.units()
+    plan.close()
+    assert int(ch["nbytes"][0]) == 1 << 20 and int(ch["meta"][0] & 0xFFFFFF) == 63
+    want = sorted(range(n), key=lambda i: (-int(reqs["length"][i]), int(reqs["key_idx"][i]), i))
+    assert [int(o) for o in ch["offset"]] == [int(reqs["offset"][i]) for i in want]
 
 
 def test_launch_config_validation(ag, hctx):

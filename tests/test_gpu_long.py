@@ -2,11 +2,16 @@
 chunks of 16 MiB forming one continuous counter stream, and AES-256-CBC
 encryption of 4,096 chains of 1 MiB.
 
-The oracle computes sampled spans (CTR keystream is seekable: the span at
-byte a of a chunk uses counter ctr0 + a / 16) and whole sampled chains;
-properties cover every byte: the chunked batch equals the same stream cut
-into 3 + 3 + 2 GiB requests, CTR applied twice restores the input, and CBC
-decryption of the chains' output restores their input."""
+Both are checked against the oracle on every byte: the device buffers are
+copied to the host 1 GiB at a time and the oracle's threaded batch runs the
+requests of that piece (the chunks and chains do not cross 1 GiB
+boundaries).  Two properties are checked besides, as extra checks that do
+not replace the oracle: the chunked CTR batch equals the same stream cut
+into 3 + 3 + 2 GiB requests (the counter continues across request
+boundaries), and CBC decryption of the chains' output restores their
+input."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -16,6 +21,8 @@ from synth import gen, workloads
 from tests.gpu_util import ag, device_schedules, first_mismatch
 
 pytestmark = pytest.mark.gpu
+
+PIECE = 1 << 30
 
 
 @pytest.fixture(scope="module")
@@ -30,13 +37,26 @@ def device_input(nbytes):
     return gen.bytes_torch(0, gen.STREAM_DATA, nbytes, torch.device("cuda:0"))
 
 
-def ctr_span_oracle(wl, r, a, n, src):
-    """Oracle bytes a .. a+n of request r (a a multiple of 16)."""
-    iv = r["iv"].copy()
-    c = (int.from_bytes(iv[8:].tobytes(), "big") + a // 16) % (1 << 64)
-    iv[8:] = np.frombuffer(c.to_bytes(8, "big"), np.uint8)
-    kb = int(wl.key_bits[r["key_idx"]])
-    return oracle.mode(workloads.OP_CTR, wl.keys[r["key_idx"]][: kb // 8], kb, iv, src)
+def check_against_oracle(wl, d_in, d_out, label):
+    """Every request of wl against the oracle, one 1 GiB piece of the buffers
+    at a time (requests must not cross a piece boundary)."""
+    offs = wl.reqs["offset"].astype(np.uint64)
+    ends = offs + wl.reqs["length"].astype(np.uint64)
+    assert (offs // PIECE == (ends - 1) // PIECE).all()
+    threads = len(os.sched_getaffinity(0))
+    n_pieces = (wl.buf_bytes + PIECE - 1) // PIECE
+    for p in range(n_pieces):
+        lo, hi = p * PIECE, min(wl.buf_bytes, (p + 1) * PIECE)
+        mine = wl.reqs[(offs >= lo) & (offs < hi)].copy()
+        mine["offset"] -= np.uint64(lo)
+        src = d_in[lo:hi].cpu().numpy()
+        got = d_out[lo:hi].cpu().numpy()
+        want = np.empty_like(src)
+        oracle.batch(src, want, mine, wl.keys, wl.key_bits, n_threads=threads)
+        msg = first_mismatch(got, want)
+        assert msg is None, f"{label}, piece {p} (bytes {lo}..{hi}): {msg}"
+        print(f"[gpu] {label}: piece {p + 1}/{n_pieces} ({mine.size} requests) equals the "
+              f"oracle", flush=True)
 
 
 def test_ctr_8gib_continuous_stream(ctx):
@@ -51,19 +71,7 @@ def test_ctr_8gib_continuous_stream(ctx):
     plan.launch(d_s, d_in, d_out)
     torch.cuda.synchronize()
     plan.close()
-    rng = np.random.default_rng(3)
-    chunks = np.unique(np.concatenate([[0, wl.reqs.size - 1],
-                                       rng.choice(wl.reqs.size, 30, replace=False)]))
-    chunk = int(wl.reqs["length"][0])
-    for ci in chunks:
-        r = wl.reqs[ci]
-        o = int(r["offset"])
-        for start in (0, chunk - 65536, int(rng.integers(0, chunk // 16 - 4096)) * 16):
-            n = 65536
-            src = d_in[o + start:o + start + n].cpu().numpy()
-            got = d_out[o + start:o + start + n].cpu().numpy()
-            msg = first_mismatch(got, ctr_span_oracle(wl, r, start, n, src))
-            assert msg is None, f"chunk {ci} at {start}: {msg}"
+    check_against_oracle(wl, d_in, d_out, "8 GiB CTR stream")
     # the same stream cut differently (requests are limited to < 4 GiB):
     # 3 + 3 + 2 GiB with the counter continuing across them
     cuts = [0, 3 << 30, 6 << 30, nbytes]
@@ -81,14 +89,6 @@ def test_ctr_8gib_continuous_stream(ctx):
     torch.cuda.synchronize()
     plan.close()
     assert torch.equal(d_big, d_out), "chunked batch differs from 3 + 3 + 2 GiB requests"
-    del d_big
-    # CTR twice restores the input
-    back = torch.empty_like(d_in)
-    plan = a.Plan(ctx, wl.reqs, 1, nbytes)
-    plan.launch(d_s, d_out, back)
-    torch.cuda.synchronize()
-    plan.close()
-    assert torch.equal(back, d_in), "CTR twice over 8 GiB"
 
 
 def test_cbc_encrypt_4096_chains_of_1mib(ctx):
@@ -103,17 +103,7 @@ def test_cbc_encrypt_4096_chains_of_1mib(ctx):
     plan.launch(d_s, d_in, d_out)
     torch.cuda.synchronize()
     plan.close()
-    rng = np.random.default_rng(4)
-    sample = np.unique(np.concatenate([[0, wl.reqs.size - 1],
-                                       rng.choice(wl.reqs.size, 14, replace=False)]))
-    kb = int(wl.key_bits[0])
-    for ci in sample:
-        r = wl.reqs[ci]
-        o, n = int(r["offset"]), int(r["length"])
-        want = oracle.mode(workloads.OP_CBC_ENC, wl.keys[0][: kb // 8], kb, r["iv"],
-                           d_in[o:o + n].cpu().numpy())
-        msg = first_mismatch(d_out[o:o + n].cpu().numpy(), want)
-        assert msg is None, f"chain {ci}: {msg}"
+    check_against_oracle(wl, d_in, d_out, "4,096 CBC-encrypt chains")
     inv = wl.reqs.copy()
     inv["op"] = workloads.OP_CBC_DEC
     back = torch.empty_like(d_in)
