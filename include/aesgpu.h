@@ -140,6 +140,28 @@ int aes_batch(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
               const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
               const aes_req_t *reqs, uint64_t n_reqs, void *stream);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): aes_batch with the
+ * same arguments, rules, results and errors, that calls no allocation
+ * routine.  The unit table (at most AES_NOALLOC_MAX_UNITS work units: one per
+ * tile of the context's tile size for CTR, ECB and CBC-decrypt requests, one
+ * per CBC-encrypt request), the in-place CBC-decrypt predecessor snapshots and
+ * the tile counters live in one fixed device array per GPU (about 24.5 MiB,
+ * held until the process ends); the requests are planned in fixed host
+ * arrays and copied from there before the call returns.  Every call on one
+ * GPU shares that GPU's array: calls whose work overlaps in time on one GPU
+ * (launched on different streams without ordering, or from several host
+ * threads) race on it and must be serialised by the caller; calls on one
+ * stream are ordered.  Host work of concurrent calls is serialised inside.
+ * CTR tiles stay in request order for both CTR variants.
+ * Errors: those of aes_batch; AES_ERR_RANGE also when the batch needs more
+ * than AES_NOALLOC_MAX_UNITS work units; AES_ERR_DEVICE also when the
+ * context's device had no scratch address (device index 64 or above). */
+#define AES_NOALLOC_MAX_UNITS (1u << 19)
+int aes_batch_noalloc(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+                      const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
+                      const aes_req_t *reqs, uint64_t n_reqs, void *stream);
+
 /* Single-mode forms of aes_batch with the requests given as parallel host
  * arrays: offsets[i], lengths[i], key_idx[i] and ivs[16*i .. 16*i+15] form
  * request i; every request uses the mode the name says (SP 800-38A 6.2 CBC

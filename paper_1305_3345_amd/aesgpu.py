@@ -40,6 +40,7 @@ AES_OP_CTR = 2
 AES_OP_ECB_ENC = 3
 AES_OP_ECB_DEC = 4
 AES_DEVICE_NONE = -1
+AES_NOALLOC_MAX_UNITS = 1 << 19
 AES_CTR_TABLE = 0
 AES_CTR_BITSLICE = 1
 
@@ -91,6 +92,7 @@ def lib():
             "aes_ctx_create": (i32, [i32, ctypes.POINTER(p)]),
             "aes_ctx_destroy": (None, [p]),
             "aes_batch": (i32, [p, p, u32, p, p, u64, p, u64, p]),
+            "aes_batch_noalloc": (i32, [p, p, u32, p, p, u64, p, u64, p]),
             "aes_cbc_encrypt_batch": (i32, [p, p, u32, p, p, u64, p, p, p, p, u64, p]),
             "aes_cbc_decrypt_batch": (i32, [p, p, u32, p, p, u64, p, p, p, p, u64, p]),
             "aes_ctr_batch": (i32, [p, p, u32, p, p, u64, p, p, p, p, u64, p]),
@@ -242,6 +244,17 @@ def batch(ctx: Context, d_scheds, d_in, d_out, reqs: np.ndarray, buf_bytes: int 
     _check(lib().aes_batch(ctx.handle, _ptr(d_scheds), _sched_count(d_scheds, n_scheds),
                            _ptr(d_in), _ptr(d_out), bb, reqs.ctypes.data, reqs.size,
                            _stream(stream)), "aes_batch")
+
+
+def batch_noalloc(ctx: Context, d_scheds, d_in, d_out, reqs: np.ndarray,
+                  buf_bytes: int | None = None, n_scheds: int | None = None, stream=None):
+    """aes_batch_noalloc (aes_batch without any allocation) over a REQ_DTYPE
+    request array."""
+    reqs = np.ascontiguousarray(reqs, dtype=REQ_DTYPE)
+    bb = _nbytes(d_in) if buf_bytes is None else buf_bytes
+    _check(lib().aes_batch_noalloc(ctx.handle, _ptr(d_scheds), _sched_count(d_scheds, n_scheds),
+                                   _ptr(d_in), _ptr(d_out), bb, reqs.ctypes.data, reqs.size,
+                                   _stream(stream)), "aes_batch_noalloc")
 
 
 def _single(name, ctx, d_scheds, d_in, d_out, offsets, lengths, key_idx, ivs, buf_bytes,

@@ -587,6 +587,187 @@ int run_batch(aes_ctx *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
     return AES_OK;
 }
 
+// ------------------------------------------------- batches without allocation
+
+// aes_batch_noalloc keeps its unit table, in-place predecessor snapshots and
+// tile counters in one fixed device array per GPU (`scratch`), and plans on
+// the host into fixed static arrays, so that a call allocates nothing.  Its
+// device address is taken once per device when a context is created there
+// (host code never uses the array's name for device memory).  Every call on a
+// device shares that device's array: calls that overlap in time on one device
+// (other streams, or other host threads) race on it.
+constexpr uint64_t NOALLOC_UNITS_BYTES = (uint64_t)AES_NOALLOC_MAX_UNITS * sizeof(Unit);
+constexpr uint64_t NOALLOC_PREDS_BYTES = (uint64_t)AES_NOALLOC_MAX_UNITS * 16;
+constexpr uint64_t NOALLOC_CTRS_OFF = NOALLOC_UNITS_BYTES + NOALLOC_PREDS_BYTES;
+constexpr uint64_t NOALLOC_SCRATCH_BYTES =
+    NOALLOC_CTRS_OFF + 2 * (uint64_t)TILE_CTRS * sizeof(uint32_t);
+
+static __device__ __align__(256) uint8_t scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES];  // device address of `scratch`, per device
+
+// Host side of a call: the unit table is built here and copied from here;
+// the ranges hold the disjointness check of unsorted requests.  Guarded by
+// g_noalloc_mu for the whole of a call's host work.
+std::mutex g_noalloc_mu;
+Unit g_noalloc_units[AES_NOALLOC_MAX_UNITS];
+std::pair<uint64_t, uint64_t> g_noalloc_ranges[AES_NOALLOC_MAX_UNITS];
+
+// Takes the device address of `scratch` on the current device (once per
+// device).  The caller has made `device` current.
+int noalloc_setup(int device) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES)
+        return AES_OK;  // such a device has no scratch; its no-allocation calls fail
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device])
+        return AES_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol);
+    g_scratch_ptr[device] = p;
+    return AES_OK;
+}
+
+int run_batch_noalloc(aes_ctx *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+                      const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
+                      const aes_req_t *reqs, uint64_t n, void *stream) {
+    if (!ctx)
+        return AES_ERR_ARG;
+    int st = check_buffers(d_in, d_out, buf_bytes, n, d_scheds);
+    if (st)
+        return st;
+    if (n && !reqs)
+        return AES_ERR_ARG;
+    // 1. The per-request rules (as validate), order, and the unit counts.
+    const uint32_t tile = ctx->tile_bytes;
+    uint64_t n_dec = 0, n_ctr = 0, n_ecb = 0, n_chain = 0, n_live = 0, payload = 0;
+    uint64_t dec_bytes = 0, ctr_bytes = 0, last_off = 0;
+    bool sorted = true, pred_in = false;
+    for (uint64_t i = 0; i < n; i++) {
+        const aes_req_t &r = reqs[i];
+        if (r.op > AES_OP_ECB_DEC)
+            return AES_ERR_ARG;
+        if ((st = check_request(r.op, r.offset, r.length, r.key_idx, n_scheds, buf_bytes)))
+            return st;
+        if (!r.length)
+            continue;
+        if (r.offset < last_off)
+            sorted = false;
+        last_off = r.offset;
+        n_live++;
+        payload += r.length;
+        const uint64_t t = (r.length + tile - 1) / tile;
+        if (r.op == AES_OP_CBC_ENC) {
+            n_chain++;
+        } else if (is_dec_tile_op(r.op)) {
+            n_dec += t;
+            dec_bytes += r.length;
+            pred_in |= r.op == AES_OP_CBC_DEC && t > 1;
+        } else {
+            (r.op == AES_OP_CTR ? n_ctr : n_ecb) += t;
+            ctr_bytes += r.length;
+        }
+    }
+    const uint64_t n_units = n_dec + n_ctr + n_ecb + n_chain;
+    if (n_units > AES_NOALLOC_MAX_UNITS)
+        return AES_ERR_RANGE;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    // 2. Disjoint output ranges: a linear scan in offset order, else a sort
+    //    of (offset, end) pairs in the static array (n_live <= n_units).
+    if (sorted) {
+        uint64_t end = 0;
+        bool any = false;
+        for (uint64_t i = 0; i < n; i++) {
+            if (!reqs[i].length)
+                continue;
+            if (any && reqs[i].offset < end)
+                return AES_ERR_OVERLAP;
+            end = reqs[i].offset + reqs[i].length;
+            any = true;
+        }
+    } else {
+        uint64_t k = 0;
+        for (uint64_t i = 0; i < n; i++)
+            if (reqs[i].length)
+                g_noalloc_ranges[k++] = {reqs[i].offset, reqs[i].offset + reqs[i].length};
+        std::sort(g_noalloc_ranges, g_noalloc_ranges + k);
+        for (uint64_t i = 1; i < k; i++)
+            if (g_noalloc_ranges[i].first < g_noalloc_ranges[i - 1].second)
+                return AES_ERR_OVERLAP;
+    }
+    if (!payload)
+        return AES_OK;
+    if (ctx->device == AES_DEVICE_NONE)
+        return AES_ERR_DEVICE;
+    void *d_scratch =
+        ctx->device < NOALLOC_MAX_DEVICES ? g_scratch_ptr[ctx->device] : nullptr;
+    if (!d_scratch)
+        return AES_ERR_DEVICE;
+    // 3. Unit records, as plan_units cuts them: [CBC/ECB-decrypt tiles | CTR
+    //    tiles | ECB-encrypt tiles | chains], tiles in request order, chains
+    //    longest first (equal lengths by key index, then offset).
+    Unit *w_dec = g_noalloc_units, *w_ctr = w_dec + n_dec, *w_ecb = w_ctr + n_ctr;
+    Unit *w_chain = w_ecb + n_ecb;
+    for (uint64_t i = 0; i < n; i++) {
+        const aes_req_t &r = reqs[i];
+        if (!r.length)
+            continue;
+        const uint32_t meta = r.key_idx | (r.op << META_OP_SHIFT);
+        if (r.op == AES_OP_CBC_ENC) {
+            Unit &u = *w_chain++;
+            u.off = r.offset;
+            u.nbytes = (uint32_t)r.length;
+            u.meta = meta;
+            for (int j = 0; j < 4; j++)
+                u.w[j] = le32(r.iv + 4 * j);
+            continue;
+        }
+        const uint64_t ctr0 = be64(r.iv + 8);
+        for (uint64_t pos = 0; pos < r.length; pos += tile) {
+            Unit &u = r.op == AES_OP_CTR ? *w_ctr++ : r.op == AES_OP_ECB_ENC ? *w_ecb++ : *w_dec++;
+            u.off = r.offset + pos;
+            u.nbytes = (uint32_t)std::min<uint64_t>(tile, r.length - pos);
+            u.meta = meta;
+            if (r.op == AES_OP_CTR) {
+                const uint64_t c = ctr0 + pos / 16;  // mod 2^64, nonce untouched
+                u.w[0] = le32(r.iv);
+                u.w[1] = le32(r.iv + 4);
+                u.w[2] = (uint32_t)c;
+                u.w[3] = (uint32_t)(c >> 32);
+            } else if (r.op == AES_OP_CBC_DEC && pos == 0) {
+                for (int j = 0; j < 4; j++)
+                    u.w[j] = le32(r.iv + 4 * j);
+            } else {
+                if (r.op == AES_OP_CBC_DEC)
+                    u.meta |= FLAG_PRED_IN;
+                u.w[0] = u.w[1] = u.w[2] = u.w[3] = 0;
+            }
+        }
+    }
+    Unit *chains = g_noalloc_units + n_dec + n_ctr + n_ecb;
+    std::sort(chains, chains + n_chain, [](const Unit &a, const Unit &b) {
+        const uint32_t ka = a.meta & META_KEY_MASK, kb = b.meta & META_KEY_MASK;
+        if (a.nbytes != b.nbytes)
+            return a.nbytes > b.nbytes;
+        return ka != kb ? ka < kb : a.off < b.off;
+    });
+    // 4. Upload (the static host array is read before the copy call returns,
+    //    as for any copy from pageable memory), zero the tile counters, launch.
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipMemcpyAsync(d_scratch, g_noalloc_units, n_units * sizeof(Unit),
+                           hipMemcpyHostToDevice, (hipStream_t)stream));
+    uint32_t *d_ctrs = (uint32_t *)((uint8_t *)d_scratch + NOALLOC_CTRS_OFF);
+    int e = launch_zero_words(d_ctrs, 2 * TILE_CTRS, stream);
+    if (e)
+        return hip_fail((hipError_t)e);
+    const PlanView v{d_scratch, d_ctrs, (size_t)n_dec, (size_t)(n_ctr + n_ecb), (size_t)n_chain,
+                     pred_in, dec_bytes, ctr_bytes, (size_t)n_ecb};
+    return launch_planned(ctx, v, d_scheds, n_scheds, d_in, d_out, stream);
+}
+
 // --------------------------------------------- large single-op calls, in parallel
 
 // Requests per chunk of the parallel single-call path, and the smallest call
@@ -859,6 +1040,11 @@ int aes_ctx_create(int hip_device, aes_ctx_t **out) {
             delete ctx;
             return hip_fail(e);
         }
+        if (int st = noalloc_setup(hip_device)) {
+            (void)hipFree(ctx->d_timg);
+            delete ctx;
+            return st;
+        }
         for (Slot &s : ctx->slots) {
             if ((e = hipEventCreateWithFlags(&s.ev, hipEventDisableTiming)) != hipSuccess ||
                 (e = hipEventCreateWithFlags(&s.copied, hipEventDisableTiming)) != hipSuccess) {
@@ -907,6 +1093,13 @@ int aes_batch(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
               const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes, const aes_req_t *reqs,
               uint64_t n_reqs, void *stream) {
     return run_batch(ctx, d_scheds, n_scheds, d_in, d_out, buf_bytes, reqs, n_reqs, stream);
+}
+
+int aes_batch_noalloc(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
+                      const uint8_t *d_in, uint8_t *d_out, uint64_t buf_bytes,
+                      const aes_req_t *reqs, uint64_t n_reqs, void *stream) {
+    return run_batch_noalloc(ctx, d_scheds, n_scheds, d_in, d_out, buf_bytes, reqs, n_reqs,
+                             stream);
 }
 
 int aes_cbc_encrypt_batch(aes_ctx_t *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,

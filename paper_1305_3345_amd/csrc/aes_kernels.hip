@@ -257,4 +257,18 @@ int launch_snapshot_preds(const Unit *d_units, uint32_t n_units, const uint8_t *
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_zero_words(uint32_t *p, uint32_t n) {
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i < n)
+        p[i] = 0u;
+}
+
+int launch_zero_words(uint32_t *d_words, uint32_t n, void *stream) {
+    if (!n)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_zero_words, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                       d_words, n);
+    return hipGetLastError();
+}
+
 }  // namespace aesgpu

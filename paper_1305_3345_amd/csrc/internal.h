@@ -103,6 +103,9 @@ int launch_request(const aes_req_t &r, uint32_t tile, const aes_schedule_t *d_sc
 // to d_preds[16u..16u+15] before the tile kernel overwrites those bytes.
 int launch_snapshot_preds(const Unit *d_units, uint32_t n_units, const uint8_t *d_in,
                           void *d_preds, void *stream);
+// Sets n words of device memory to zero with a kernel (a fill that stream
+// capture records as a kernel node, not as a memset node).
+int launch_zero_words(uint32_t *d_words, uint32_t n, void *stream);
 
 // Records a failing hipError_t for aes_last_hip_error and returns
 // AES_ERR_DEVICE (aes_abi.cpp).
