@@ -26,10 +26,23 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 UNIT_BYTES = 32  # one work-unit record read per tile
 SCHED_BYTES = 512
-# Conflict-free ds_read_b32 lane-gathers per second on the whole chip, as a
-# probe of dependent ds_read_b32 chains measured it (31.0 per clock per CU,
-# 97% of the 32 addresses the LDS serves per clock).
-LDS_GATHER_CEILING = 1.83e13
+PROBE = os.path.join(ROOT, "paper_1305_3345_amd", "probe", "lds_gather_probe")
+
+
+def lds_probe():
+    """The LDS gather ceiling of this machine, measured now: conflict-free
+    ds_read_b32 lane-gathers per second over the chip, per clock per compute
+    unit, and the shader clock during the probe (the probe program is a
+    child process, started before this process touches the GPU)."""
+    import subprocess
+    if not os.path.exists(PROBE):
+        raise RuntimeError(f"{PROBE} is missing: build it with "
+                           "`python -m paper_1305_3345_amd.build`")
+    out = subprocess.run([PROBE, "0"], stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                         text=True, timeout=120)
+    if out.returncode != 0:
+        raise RuntimeError(f"LDS probe failed: {out.stderr.strip()}")
+    return json.loads(out.stdout.strip().splitlines()[-1])
 
 
 def lds_gathers_per_block(run: str) -> int:
@@ -55,10 +68,13 @@ def parse():
                     help="comma-separated subset of the step's runs (for profiling)")
     ap.add_argument("--skip-serving", action="store_true",
                     help="skip the serving (Poisson arrivals, p50/p99) measurement")
-    ap.add_argument("--serve-requests", type=int, default=2000,
+    ap.add_argument("--serve-requests", type=int, default=20000,
                     help="measured requests per arrival rate and engine")
-    ap.add_argument("--serve-warmup", type=int, default=200,
+    ap.add_argument("--serve-warmup", type=int, default=2000,
                     help="warm-up requests before the measured ones, per rate and engine")
+    ap.add_argument("--skip-lds-probe", action="store_true",
+                    help="leave out the LDS gather probe (its ceiling is then null); for "
+                         "profiler runs, which would also profile the probe's process")
     ap.add_argument("--skip-host-serving", action="store_true",
                     help="skip serving with payloads in pinned host memory")
     ap.add_argument("--skip-variants", action="store_true",
@@ -552,6 +568,7 @@ def bench_serving(dev, n_measure=2000, n_warm=200):
             sel = lat[ops == op]
             out[f"{nm}_p50_us"] = round(float(np.percentile(sel, 50)), 1)
             out[f"{nm}_p99_us"] = round(float(np.percentile(sel, 99)), 1)
+            out[f"{nm}_p999_us"] = round(float(np.percentile(sel, 99.9)), 1)
         gpu = (m["gpu_done_ticks"].astype(np.int64) - m["gpu_dispatch_ticks"].astype(np.int64))
         if gpu.any():  # persistent engine: device clock, 100 MHz, dispatch -> last unit done
             for op, nm in ((workloads.OP_CBC_ENC, "enc"), (workloads.OP_CBC_DEC, "dec")):
@@ -736,6 +753,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    # The LDS ceiling first, in a child process, before this one uses the GPU.
+    probe = None if args.skip_lds_probe else lds_probe()
+
     import numpy as np
     import torch
 
@@ -835,10 +855,16 @@ def main():
     # The ceiling that binds the table rounds: LDS gathers (one ds_read_b32
     # lane per table lookup) against the rate a ds_read_b32 probe measured.
     g_rate = d["gathers"] / d["launches"] / avg_ms * 1e3
-    roofline["lds_gathers"] = {"achieved": float(f"{g_rate:.4g}"), "ceiling": LDS_GATHER_CEILING,
-                               "unit": "lane-gathers/s",
-                               "frac": round(g_rate / LDS_GATHER_CEILING, 4),
-                               "per_launch": int(d["gathers"] / d["launches"])}
+    ceiling = probe["lane_gathers_per_s"] if probe else None
+    roofline["lds_gathers"] = {
+        "achieved": float(f"{g_rate:.4g}"),
+        "ceiling": float(f"{ceiling:.4g}") if ceiling else None,
+        "unit": "lane-gathers/s",
+        "frac": round(g_rate / ceiling, 4) if ceiling else None,
+        "per_launch": int(d["gathers"] / d["launches"]),
+        "ceiling_source": ("lds_gather_probe in this run: "
+                           f"{probe['lane_gathers_per_clk_per_cu']} lane-gathers per clock per "
+                           f"compute unit at {probe['sclk_ghz']} GHz") if probe else None}
 
     # Host-metadata single-call form: validation, planning and the unit-table
     # upload happen inside every call (end-to-end, reported beside the value).

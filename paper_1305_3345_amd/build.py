@@ -8,6 +8,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libaesgpu.so")
+# The LDS gather probe (a stand-alone program the benchmark runs to measure
+# the ceiling of the round-table kernels on the box it runs on).
+PROBE_SRC = os.path.join(HERE, "probe", "lds_gather_probe.cpp")
+PROBE = os.path.join(HERE, "probe", "lds_gather_probe")
 
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -63,7 +67,22 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    build_probe(verbose)
     return LIB
+
+
+def build_probe(verbose: bool = False) -> str:
+    """Compiles the LDS gather probe (always) and returns its path."""
+    tmp = PROBE + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17"] + NO_PK_FP32 + [
+        "-x", "hip", PROBE_SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    out = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if out.returncode != 0:
+        raise RuntimeError("probe build failed:\n" + out.stdout)
+    os.replace(tmp, PROBE)
+    return PROBE
 
 
 if __name__ == "__main__":
