@@ -89,6 +89,9 @@ def parse():
                     help="also time all 10,000 mixed requests as one launch each and as a "
                          "graph of those launches (CBC-encrypt chains then run one after "
                          "another: about 20 s per form)")
+    ap.add_argument("--batched-no-per-request", action="store_true",
+                    help="batched section without the per-request launches of the parallel "
+                         "subset (for profiler runs, where each of those launches is slow)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also copy the 256 MiB input once device-to-device (a kernel of "
                          "known traffic for scaling hardware byte counters)")
@@ -212,7 +215,7 @@ def time_gpu(fn, iters, stream):
     return ms[len(ms) // 2]
 
 
-def bench_batched(dev, iters=3, full_per_request=False):
+def bench_batched(dev, iters=3, full_per_request=False, per_request=True):
     """The batched form: 10,000 uneven requests (4 KiB..1 MiB, mixed ops, 64
     keys of 128/256 bits) as one autotuned fused launch, against one kernel
     launch per request and a HIP graph of those launches (on the requests of
@@ -254,10 +257,12 @@ def bench_batched(dev, iters=3, full_per_request=False):
     par_bytes = int(par["length"].sum())
     p_par = aesgpu.Plan(ctx, par, wl.keys.shape[0], nbytes)
     par_batched_ms = time_gpu(lambda: p_par.launch(d_s, d_in, d_out, stream=stream), iters, stream)
-    par_each_ms = time_gpu(lambda: aesgpu.request_launches(ctx, d_s, d_in, d_out, par,
-                                                           stream=stream), iters, stream)
-    g_each = aesgpu.Graph.of_requests(ctx, d_s, d_in, d_out, par)
-    par_graph_ms = time_gpu(lambda: g_each.launch(stream), iters, stream)
+    par_each_ms = par_graph_ms = g_each = None
+    if per_request:
+        par_each_ms = time_gpu(lambda: aesgpu.request_launches(ctx, d_s, d_in, d_out, par,
+                                                               stream=stream), iters, stream)
+        g_each = aesgpu.Graph.of_requests(ctx, d_s, d_in, d_out, par)
+        par_graph_ms = time_gpu(lambda: g_each.launch(stream), iters, stream)
     full = None
     if full_per_request:
         def once(fn):
@@ -282,9 +287,10 @@ def bench_batched(dev, iters=3, full_per_request=False):
                 "per_request_graph_gbs": round(info["payload_bytes"] / graph_ms / 1e6, 2),
                 "note": "one timed pass each (no warm-up pass)"}
     for o in (g_plan, g_each, plan, p_long, p_par):
-        o.close()
+        if o is not None:
+            o.close()
     ctx.close()
-    gbs = lambda b, ms: round(b / ms / 1e6, 1)
+    gbs = lambda b, ms: None if ms is None else round(b / ms / 1e6, 1)
     return {
         "workload": f"{wl.reqs.size} requests, 4 KiB..1 MiB log-uniform, ops "
                     f"{int((wl.reqs['op'] == 0).sum())} CBC-enc / {int((wl.reqs['op'] == 1).sum())} "
@@ -303,8 +309,8 @@ def bench_batched(dev, iters=3, full_per_request=False):
             "per_request_launches_gbs": gbs(par_bytes, par_each_ms),
             "per_request_graph_gbs": gbs(par_bytes, par_graph_ms),
             "one_launch_ms": round(par_batched_ms, 3),
-            "per_request_launches_ms": round(par_each_ms, 3),
-            "per_request_graph_ms": round(par_graph_ms, 3),
+            "per_request_launches_ms": None if par_each_ms is None else round(par_each_ms, 3),
+            "per_request_graph_ms": None if par_graph_ms is None else round(par_graph_ms, 3),
         },
     }
 
@@ -909,7 +915,8 @@ def main():
 
     batched = None
     if not args.skip_batched:
-        batched = bench_batched(dev, full_per_request=args.batched_full_per_request)
+        batched = bench_batched(dev, full_per_request=args.batched_full_per_request,
+                                per_request=not args.batched_no_per_request)
 
     long_stream = None
     if not args.skip_long:

@@ -12,8 +12,10 @@
 //
 // Reports (one JSON line): lane-gathers per second over the chip (lookups /
 // kernel time from HIP events), lane-gathers per shader clock per compute
-// unit (s_memtime), and the shader clock during the run (s_memtime ticks over
-// s_memrealtime's 100 MHz ticks).  A checksum of the chains' end points keeps
+// unit (s_memtime), the shader clock during the run (s_memtime ticks over
+// s_memrealtime's 100 MHz ticks), and the latency of one lookup that depends
+// on the one before (one wave per compute unit, one chain; shader clocks per
+// lookup, loop included).  A checksum of the chains' end points keeps
 // the lookups live.
 #include <hip/hip_runtime.h>
 
@@ -80,6 +82,28 @@ __global__ __launch_bounds__(THREADS) void k_probe(uint32_t steps, uint32_t *sin
     }
 }
 
+// Latency: one wave per compute unit walking one chain, so every lookup
+// waits for the one before; s_memtime ticks per lookup.
+__global__ __launch_bounds__(64) void k_latency(uint32_t steps, uint32_t *sink,
+                                                unsigned long long *ticks) {
+    __shared__ uint32_t lds[LDS_BYTES / 4];
+    const uint32_t slot = (threadIdx.x & 31u) << 2;
+    for (uint32_t w = threadIdx.x; w < LDS_BYTES / 4; w += blockDim.x) {
+        const uint32_t byte = w << 2;
+        const uint32_t g = byte >> 16, x = (byte >> 8) & 255u, h = (byte >> 7) & 1u;
+        lds[w] = (g << 16) | (((x * 29u + 71u + h) & 255u) << 8) | (h << 7) | (byte & 127u);
+    }
+    __syncthreads();
+    uint32_t a = (((threadIdx.x * 7u + blockIdx.x) & 255u) << 8) | slot;
+    const unsigned long long t0 = __builtin_amdgcn_s_memtime();
+    for (uint32_t i = 0; i < steps; i++)
+        a = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(lds) + a);
+    const unsigned long long t1 = __builtin_amdgcn_s_memtime();
+    atomicXor(sink, a);
+    if (threadIdx.x == 0)
+        ticks[blockIdx.x] = t1 - t0;
+}
+
 }  // namespace
 
 int main(int argc, char **argv) {
@@ -129,14 +153,25 @@ int main(int argc, char **argv) {
         std::sort(v.begin(), v.end());
         return v[v.size() / 2];
     };
+    // Latency of one dependent lookup (median over the compute units).
+    const uint32_t lat_steps = 4096;
+    hipLaunchKernelGGL(k_latency, dim3(n_cu), dim3(64), 0, 0, lat_steps, sink, ticks);
+    CHECK(hipGetLastError());
+    CHECK(hipDeviceSynchronize());
+    CHECK(hipMemcpy(h.data(), ticks, sizeof(unsigned long long) * n_cu, hipMemcpyDeviceToHost));
+    std::vector<double> lat;
+    for (int g = 0; g < n_cu; g++)
+        lat.push_back((double)h[g] / lat_steps);
+    const double lat_clk = med(lat);
     const double ms = med(ms_all);
     const double total = (double)n_cu * THREADS * CHAINS * steps;
     printf("{\"probe\": \"lds_gather\", \"device\": \"%s\", \"compute_units\": %d, "
            "\"workgroup_threads\": %d, \"chains_per_lane\": %d, \"steps\": %u, \"reps\": %d, "
            "\"kernel_ms_median\": %.4f, \"lane_gathers_per_s\": %.4e, "
-           "\"lane_gathers_per_clk_per_cu\": %.3f, \"sclk_ghz\": %.3f}\n",
+           "\"lane_gathers_per_clk_per_cu\": %.3f, \"sclk_ghz\": %.3f, "
+           "\"dependent_lookup_clk\": %.1f}\n",
            prop.gcnArchName, n_cu, THREADS, CHAINS, steps, reps, ms, total / (ms * 1e-3),
-           med(per_clk_all), med(ghz_all));
+           med(per_clk_all), med(ghz_all), lat_clk);
     CHECK(hipFree(sink));
     CHECK(hipFree(ticks));
     return 0;
