@@ -22,7 +22,7 @@ NO_PK_FP32 = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 # Per-file instruction-scheduling strategy (LLVM AMDGPU), chosen by measuring
 # the tile kernels on 4 KiB pages: see each file's header.
 SCHED_FLAGS = {
-    "aes_tiles_dec.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
+    "aes_tiles_dec.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
 }
 
 
