@@ -316,9 +316,10 @@ def bench_batched(dev, iters=3, full_per_request=False, per_request=True):
 
 
 def bench_variants(ctx, n_pages, d_in, d_out, dev, iters=5):
-    """The CTR kernel variants side by side on the 4 KiB-page workload: round
-    tables in LDS against the bitsliced kernel, AES-128 and AES-256 (plan
-    launches, median of iters, HIP events)."""
+    """The kernel variants side by side on the 4 KiB-page workload: round
+    tables in LDS against the bitsliced kernels, for CTR and for CBC
+    decryption, AES-128 and AES-256 (plan launches, median of iters, HIP
+    events)."""
     import torch
 
     from paper_1305_3345_amd import aesgpu
@@ -341,6 +342,20 @@ def bench_variants(ctx, n_pages, d_in, d_out, dev, iters=5):
                 rec[vname] = {"ms": round(ms, 4), "gbs_payload": round(payload / ms / 1e6, 1)}
             rec["bitslice_over_table"] = round(rec["table"]["ms"] / rec["bitslice"]["ms"], 3)
             out[f"ctr_{bits}"] = rec
+        ctx.set_config(**cfg)
+        for bits in (128, 256):
+            wl = workloads.config2(workloads.OP_CBC_DEC, bits, n_pages=n_pages)
+            d_s = aesgpu.schedules_to_device(aesgpu.expand_keys(wl.keys, wl.key_bits), dev)
+            payload = int(wl.reqs["length"].sum())
+            rec = {}
+            for v, vname in ((aesgpu.AES_DEC_TABLE, "table"), (aesgpu.AES_DEC_BITSLICE, "bitslice")):
+                ctx.set_config(dec_variant=v)
+                plan = aesgpu.Plan(ctx, wl.reqs, wl.keys.shape[0], wl.buf_bytes)
+                ms = time_gpu(lambda: plan.launch(d_s, d_in, d_out, stream=stream), iters, stream)
+                plan.close()
+                rec[vname] = {"ms": round(ms, 4), "gbs_payload": round(payload / ms / 1e6, 1)}
+            rec["bitslice_over_table"] = round(rec["table"]["ms"] / rec["bitslice"]["ms"], 3)
+            out[f"cbc_dec_{bits}"] = rec
     finally:
         ctx.set_config(**cfg)
     return out
@@ -605,6 +620,54 @@ def bench_serving(dev, n_measure=2000, n_warm=200):
     return {"workload": f"{n_measure} measured (+{n_warm} warm-up) requests per rate and engine, "
                         "Poisson arrivals, 4..64 KiB, AES-128-CBC enc/dec 50/50, 256 key slots",
             "saturation_req_s": sat, "rates": rates}
+
+
+def bench_beside_server(dev, n_pages=65536, reps=5):
+    """A batch call while a persistent server is live: the server's
+    workgroups hold their compute units (each a whole CU's LDS) until its
+    idle timeout, so a tile launch issued meanwhile runs on the others.  One
+    AES-128 CTR plan launch over n_pages pages, alone and beside an idle
+    persistent server of the default grid and of a 4-workgroup grid (a
+    request is submitted before each timed launch so the kernel is running)."""
+    import numpy as np
+    import torch
+
+    from paper_1305_3345_amd import aesgpu
+    from synth import gen, workloads
+
+    wl = workloads.config2(workloads.OP_CTR, 128, n_pages=n_pages)
+    nbytes = wl.buf_bytes
+    d_in = gen.bytes_torch(0, gen.STREAM_DATA, nbytes, dev)
+    d_out = torch.empty_like(d_in)
+    scheds = aesgpu.expand_keys(wl.keys, wl.key_bits)
+    d_s = aesgpu.schedules_to_device(scheds, dev)
+    stream = torch.cuda.current_stream()
+    ctx = aesgpu.Context(0)
+    plan = aesgpu.Plan(ctx, wl.reqs, wl.keys.shape[0], nbytes)
+    out = {"workload": f"AES-128 CTR plan launch, {n_pages} x 4 KiB pages, median of {reps}",
+           "alone_ms": round(time_gpu(lambda: plan.launch(d_s, d_in, d_out, stream=stream), reps,
+                                      stream), 4)}
+    small = torch.zeros(4096, dtype=torch.uint8, device=dev)
+    for label, nwg in (("beside_default_grid_ms", 0), ("beside_4_workgroups_ms", 4)):
+        with aesgpu.Server(ctx, mode=aesgpu.AES_SERVE_PERSISTENT, key_slots=1,
+                           n_workgroups=nwg) as srv:
+            srv.set_key(0, scheds[0])
+            ms = []
+            for _ in range(reps + 1):
+                t = srv.submit(workloads.OP_CTR, 0, bytes(16), small, small, 4096)
+                srv.wait(t)  # the persistent kernel is now running (idle until its timeout)
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                plan.launch(d_s, d_in, d_out, stream=stream)
+                b.record(stream)
+                b.synchronize()
+                ms.append(a.elapsed_time(b))
+            ms = sorted(ms[1:])
+            out[label] = round(ms[len(ms) // 2], 4)
+    plan.close()
+    ctx.close()
+    return out
 
 
 def bench_host_serving(dev, n_measure=1000, n_warm=100, reps=15):
@@ -909,6 +972,10 @@ def main():
     if not args.skip_serving:
         serving = bench_serving(dev, n_measure=args.serve_requests, n_warm=args.serve_warmup)
 
+    beside = None
+    if not args.skip_serving:
+        beside = bench_beside_server(dev, n_pages)
+
     host_serving = None
     if not args.skip_host_serving:
         host_serving = bench_host_serving(dev)
@@ -959,11 +1026,15 @@ def main():
         "per_run": per_run,
         "hbm_copy_gbs": round(copy_gbs, 1),
         "per_call": per_call,
-        "ctr_variants": variants,
+        "ctr_variants": ({k: v for k, v in variants.items() if k.startswith("ctr")}
+                         if variants else None),
+        "dec_variants": ({k: v for k, v in variants.items() if k.startswith("cbc_dec")}
+                         if variants else None),
         "batched": batched,
         "long_stream": long_stream,
         "e2_size_sweep": e2,
         "serving": serving,
+        "batch_beside_live_server": beside,
         "host_serving": host_serving,
     }
     for _, _, plan, _, _, _, _ in runs:

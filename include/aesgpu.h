@@ -250,7 +250,7 @@ int aes_plan_info(const aes_plan_t *plan, aes_plan_info_t *info);
  * equal length by key index) to out and sets *n_out to the plan's total unit count.
  * CTR and ECB-encrypt tiles are in request order, or, when the context's CTR
  * variant was AES_CTR_BITSLICE at planning time, grouped by key with request
- * order kept within a key. */
+ * order kept within a key; decryption tiles likewise with AES_DEC_BITSLICE. */
 int aes_plan_units(const aes_plan_t *plan, aes_unit_t *out, uint64_t max, uint64_t *n_out);
 /* Waits for the device to be idle, then frees the plan.  NULL is a no-op. */
 void aes_plan_destroy(aes_plan_t *plan);
@@ -280,7 +280,9 @@ typedef struct aes_launch_config {
     uint32_t chain_quad;  /* CBC-encrypt chains: 0 = chain_lanes chains per wave, one lane each;
                              1 = 16 chains per wave, four lanes each (one state column per
                              lane: a quarter of the lookups per lane per round) */
-    uint32_t reserved[4];
+    uint32_t dec_variant; /* CBC- and ECB-decrypt units of batches and plans: AES_DEC_TABLE or
+                             AES_DEC_BITSLICE (not tuned: aes_tune and its cache keep it) */
+    uint32_t reserved[3];
 } aes_launch_config_t;
 
 /* CTR kernel variants.  AES_CTR_TABLE: round tables in LDS, one block per
@@ -291,6 +293,14 @@ typedef struct aes_launch_config {
  * launches and the serving engines always use the table kernels. */
 #define AES_CTR_TABLE 0u
 #define AES_CTR_BITSLICE 1u
+/* Decryption kernel variants (CBC and ECB decryption; FIPS-197 5.3).
+ * AES_DEC_TABLE: the equivalent inverse cipher with round tables in LDS.
+ * AES_DEC_BITSLICE: the inverse cipher on 32 blocks per lane as bit planes,
+ * the inverse S-box as a tower-field circuit; the planner orders decryption
+ * tiles by key.  Per-request launches and the serving engines always use
+ * the table kernels. */
+#define AES_DEC_TABLE 0u
+#define AES_DEC_BITSLICE 1u
 
 int aes_ctx_get_config(const aes_ctx_t *ctx, aes_launch_config_t *cfg);
 /* Errors: AES_ERR_ARG for an unsupported shape (nothing changes). */

@@ -43,6 +43,8 @@ AES_DEVICE_NONE = -1
 AES_NOALLOC_MAX_UNITS = 1 << 19
 AES_CTR_TABLE = 0
 AES_CTR_BITSLICE = 1
+AES_DEC_TABLE = 0
+AES_DEC_BITSLICE = 1
 
 SCHED_DTYPE = np.dtype([("key_bits", "<u4"), ("nr", "<u4"), ("reserved0", "<u4", (2,)),
                         ("ek", "<u4", (60,)), ("dk", "<u4", (60,)), ("reserved1", "<u4", (4,))])
@@ -56,7 +58,7 @@ PLAN_INFO_DTYPE = np.dtype([("n_units_cbc_dec", "<u8"), ("n_units_ctr", "<u8"),
                             ("reserved", "<u4")])
 CONFIG_DTYPE = np.dtype([(k, "<u4") for k in (
     "tile_bytes", "ctr_nb", "ctr_wg", "dec_nb", "dec_wg", "chain_lanes", "chain_wg", "mixed_nb",
-    "fuse", "grid", "ctr_variant", "chain_quad")] + [("reserved", "<u4", (4,))])
+    "fuse", "grid", "ctr_variant", "chain_quad", "dec_variant")] + [("reserved", "<u4", (3,))])
 assert CONFIG_DTYPE.itemsize == 64
 assert SCHED_DTYPE.itemsize == 512 and REQ_DTYPE.itemsize == 40 and UNIT_DTYPE.itemsize == 32
 

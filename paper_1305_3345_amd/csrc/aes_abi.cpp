@@ -200,11 +200,12 @@ void group_by_key(std::vector<Unit> &t, std::vector<Unit> &buf) {
 // tiles (a multiple of 16), CBC-encrypt into one chain each.  p is emptied
 // first (its storage kept).  Encryption-side tiles: CTR tiles, then
 // ECB-encrypt tiles (the bitsliced kernel takes only the CTR range); with
-// group_keys each of the two groups is ordered by key (request order kept
-// within a key), which the bitsliced kernel needs to share one schedule
-// across a wave's tiles -- the table kernels read a schedule per tile.
-int plan_units(const aes_req_t *reqs, uint64_t n, uint32_t tile_bytes, bool group_keys,
-               Planned &p) {
+// group_ctr each of the two groups is ordered by key (request order kept
+// within a key), and with group_dec the decryption tiles are, which the
+// bitsliced kernels need to share one schedule across a wave's tiles -- the
+// table kernels read a schedule per tile.
+int plan_units(const aes_req_t *reqs, uint64_t n, uint32_t tile_bytes, bool group_ctr,
+               bool group_dec, Planned &p) {
     p.reset();
     try {
         uint64_t n_tiles_ctr = 0, n_tiles_dec = 0, n_chain = 0;
@@ -270,10 +271,12 @@ int plan_units(const aes_req_t *reqs, uint64_t n, uint32_t tile_bytes, bool grou
                 }
             }
         }
-        if (group_keys) {
+        if (group_ctr) {
             group_by_key(p.ctr, p.sort_buf);
             group_by_key(p.ecb, p.sort_buf);
         }
+        if (group_dec)
+            group_by_key(p.dec, p.sort_buf);
         p.n_ecb = p.ecb.size();
         p.ctr.insert(p.ctr.end(), p.ecb.begin(), p.ecb.end());
         // Chains longest first across the batch, so that when there are more
@@ -322,6 +325,7 @@ struct aes_ctx {
     bool fuse = true;        // one launch for batches that mix ops
     int grid = 0;            // tile / fused kernel workgroups, 0 = one per compute unit
     uint32_t ctr_variant = AES_CTR_TABLE;
+    uint32_t dec_variant = AES_DEC_TABLE;
     hipStream_t capture = nullptr;  // private stream for graph capture and tuning
     // Scratch of the single-call forms, reused from call to call (a context
     // is used by one thread at a time): requests built from the caller's
@@ -486,6 +490,15 @@ int launch_planned(aes_ctx *ctx, const PlanView &v, const aes_schedule_t *d_sche
         if ((e = launch_snapshot_preds(u_dec, (uint32_t)v.n_dec, d_in, d_preds, stream)))
             return hip_fail((hipError_t)e);
     }
+    // The bitsliced decryption kernel takes every decryption tile in a launch
+    // of its own (the predecessor snapshots above included).
+    size_t n_dec = v.n_dec;
+    if (n_dec && ctx->dec_variant == AES_DEC_BITSLICE) {
+        if ((e = launch_dec_bitslice(u_dec, (uint32_t)n_dec, d_scheds, n_scheds, d_preds, d_in,
+                                     d_out, stream)))
+            return hip_fail((hipError_t)e);
+        n_dec = 0;
+    }
     // The bitsliced CTR kernel has a launch of its own for the CTR tiles; the
     // table kernels then take only the ECB-encrypt tiles of that range.
     const size_t n_ctr_only = v.n_ctr - v.n_ecb;
@@ -496,7 +509,7 @@ int launch_planned(aes_ctx *ctx, const PlanView &v, const aes_schedule_t *d_sche
     if (bitslice)
         u_ctr += n_ctr_only;
     const size_t n_ctr_tab = bitslice ? v.n_ecb : v.n_ctr;
-    const int kinds = (v.n_dec > 0) + (n_ctr_tab > 0) + (v.n_chain > 0);
+    const int kinds = (n_dec > 0) + (n_ctr_tab > 0) + (v.n_chain > 0);
     // One fused launch when CBC-encrypt chains share the batch with tiles: the
     // long chains then run beside the tiles on the workgroups the split gives
     // them.  Without chains, one launch per table set is faster (the tile
@@ -512,11 +525,12 @@ int launch_planned(aes_ctx *ctx, const PlanView &v, const aes_schedule_t *d_sche
         a.timg = ctx->d_timg;
         a.in = d_in;
         a.out = d_out;
-        a.n_dec = (uint32_t)v.n_dec;
+        a.n_dec = (uint32_t)n_dec;
         a.n_ctr = (uint32_t)n_ctr_tab;
         a.n_chain = (uint32_t)v.n_chain;
         a.n_sched = n_scheds;
         PlanView fused = v;
+        fused.n_dec = n_dec;
         fused.n_ctr = n_ctr_tab;
         fused.ctr_bytes = bitslice ? (v.n_ctr ? v.ctr_bytes * v.n_ecb / v.n_ctr : 0)
                                    : v.ctr_bytes;
@@ -527,7 +541,7 @@ int launch_planned(aes_ctx *ctx, const PlanView &v, const aes_schedule_t *d_sche
             return hip_fail((hipError_t)e);
         return AES_OK;
     }
-    if ((e = launch_cbcdec_tiles(u_dec, (uint32_t)v.n_dec, d_scheds, n_scheds, ctx->d_timg,
+    if ((e = launch_cbcdec_tiles(u_dec, (uint32_t)n_dec, d_scheds, n_scheds, ctx->d_timg,
                                  d_preds, d_in, d_out, v.d_ctrs, ctx->tile_dec, ctx->n_cu,
                                  stream)))
         return hip_fail((hipError_t)e);
@@ -563,7 +577,8 @@ int run_batch(aes_ctx *ctx, const aes_schedule_t *d_scheds, uint32_t n_scheds,
     if ((st = validate(reqs, n, n_scheds, buf_bytes)))
         return st;
     Planned &p = ctx->scratch_plan;
-    if ((st = plan_units(reqs, n, ctx->tile_bytes, ctx->ctr_variant == AES_CTR_BITSLICE, p)))
+    if ((st = plan_units(reqs, n, ctx->tile_bytes, ctx->ctr_variant == AES_CTR_BITSLICE,
+                         ctx->dec_variant == AES_DEC_BITSLICE, p)))
         return st;
     if (!p.payload)
         return AES_OK;
@@ -796,6 +811,7 @@ int single_parallel(uint32_t op, aes_ctx *ctx, const aes_schedule_t *d_scheds,
                     const uint8_t *ivs, uint64_t n, void *stream) {
     if (n < PAR_MIN_REQS || op == AES_OP_CBC_ENC ||
         (op == AES_OP_CTR && ctx->ctr_variant == AES_CTR_BITSLICE) ||
+        (is_dec_tile_op(op) && ctx->dec_variant == AES_DEC_BITSLICE) ||
         n / PAR_CHUNK >= (1ull << 30))
         return 1;
     int st = check_buffers(d_in, d_out, buf_bytes, n, d_scheds);
@@ -1162,7 +1178,7 @@ int aes_plan_create(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n, uint32_t 
     pl->n_scheds = n_scheds;
     pl->buf_bytes = buf_bytes;
     if ((st = plan_units(reqs, n, ctx->tile_bytes, ctx->ctr_variant == AES_CTR_BITSLICE,
-                         pl->p))) {
+                         ctx->dec_variant == AES_DEC_BITSLICE, pl->p))) {
         delete pl;
         return st;
     }
@@ -1284,6 +1300,7 @@ int aes_ctx_get_config(const aes_ctx_t *ctx, aes_launch_config_t *cfg) {
     cfg->fuse = ctx->fuse ? 1u : 0u;
     cfg->grid = (uint32_t)ctx->grid;
     cfg->ctr_variant = ctx->ctr_variant;
+    cfg->dec_variant = ctx->dec_variant;
     return AES_OK;
 }
 
@@ -1304,6 +1321,8 @@ int aes_ctx_set_config(aes_ctx_t *ctx, const aes_launch_config_t *cfg) {
         return AES_ERR_ARG;
     if (cfg->ctr_variant != AES_CTR_TABLE && cfg->ctr_variant != AES_CTR_BITSLICE)
         return AES_ERR_ARG;
+    if (cfg->dec_variant != AES_DEC_TABLE && cfg->dec_variant != AES_DEC_BITSLICE)
+        return AES_ERR_ARG;
     if (cfg->chain_quad > 1)
         return AES_ERR_ARG;
     ctx->tile_bytes = cfg->tile_bytes;
@@ -1320,6 +1339,7 @@ int aes_ctx_set_config(aes_ctx_t *ctx, const aes_launch_config_t *cfg) {
     ctx->fuse = cfg->fuse != 0;
     ctx->grid = (int)cfg->grid;
     ctx->ctr_variant = cfg->ctr_variant;
+    ctx->dec_variant = cfg->dec_variant;
     return AES_OK;
 }
 
@@ -1541,7 +1561,10 @@ int aes_tune(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_
     if (cache && *cache) {
         sig = tune_signature(ctx->arch, ctx->n_cu, reqs, n_reqs, n_scheds);
         aes_launch_config_t c;
-        if (tune_cache_lookup(cache, sig, &c) && aes_ctx_set_config(ctx, &c) == AES_OK) {
+        // The cache holds the tuned knobs; the decryption variant is the
+        // caller's and stays as set.
+        if (tune_cache_lookup(cache, sig, &c) && ((c.dec_variant = ctx->dec_variant), true) &&
+            aes_ctx_set_config(ctx, &c) == AES_OK) {
             if (best_out)
                 aes_ctx_get_config(ctx, best_out);
             return AES_OK;
@@ -1611,11 +1634,13 @@ int aes_tune(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_
     // the batch, under k (as launch_planned decides: the bitsliced variant
     // launches the CTR tiles on their own).
     auto table_tiles = [&](const aes_launch_config_t &k) {
-        return has_dec || has_ecb_enc || (has_ctr && k.ctr_variant != AES_CTR_BITSLICE);
+        return (has_dec && k.dec_variant != AES_DEC_BITSLICE) || has_ecb_enc ||
+               (has_ctr && k.ctr_variant != AES_CTR_BITSLICE);
     };
     auto fused = [&](const aes_launch_config_t &k) {
         const bool ctr_tab = has_ecb_enc || (has_ctr && k.ctr_variant != AES_CTR_BITSLICE);
-        const int kinds = (int)has_dec + (int)ctr_tab + (int)has_chains;
+        const bool dec_tab = has_dec && k.dec_variant != AES_DEC_BITSLICE;
+        const int kinds = (int)dec_tab + (int)ctr_tab + (int)has_chains;
         return k.fuse && has_chains && kinds > 1;
     };
     const uint32_t tiles[] = {4096, 8192, 16384};

@@ -1,12 +1,16 @@
-// bitslice_aes.h -- the bitsliced AES cipher (FIPS-197 section 5.1) on 32
-// blocks held as 128 bit planes, for CTR keystream on CDNA4.
+// bitslice_aes.h -- the bitsliced AES cipher (FIPS-197 section 5.1) and
+// inverse cipher (section 5.3) on 32 blocks held as 128 bit planes, for CTR
+// keystream and CBC / ECB decryption on CDNA4.
 //
 // Plane layout: P[w][8 r + k] is bit k of byte r of state word w (the word of
 // column w, little-endian), one bit per block across a 32-bit register, so
 // every Boolean operation works on 32 blocks at once:
-//   SubBytes    -- the generated tower-field S-box circuit (bitslice_sbox.h);
+//   SubBytes    -- the generated tower-field S-box circuits (bitslice_sbox.h);
 //   ShiftRows   -- register moves;
 //   MixColumns  -- out_r = xtime(a_r ^ a_(r+1)) ^ (a_(r+1) ^ a_(r+2) ^ a_(r+3));
+//   InvMixColumns -- MixColumns after multiplying each column by {04}x^2 +
+//                 {05} (the inverse polynomial {0b}x^3 + {0d}x^2 + {09}x +
+//                 {0e} is that product modulo x^4 + 1);
 //   AddRoundKey -- each key bit becomes an all-ones or all-zero mask.
 #pragma once
 #include <stdint.h>
@@ -103,36 +107,48 @@ __device__ __forceinline__ void bs_shift_rows(uint32_t P[4][32]) {
     }
 }
 
-// MixColumns and AddRoundKey (FIPS-197 5.1.3-5.1.4), in place, column by
-// column: out_r = xtime(a_r ^ a_(r+1)) ^ (a_0 ^ a_1 ^ a_2 ^ a_3) ^ a_r ^ key.
-__device__ __forceinline__ void bs_mix_key(uint32_t P[4][32], const uint32_t *__restrict__ rk) {
+// MixColumns (FIPS-197 5.1.3) of column c, in place, then with KEY the
+// round-key word kw added (5.1.4): out_r = xtime(a_r ^ a_(r+1)) ^ (a_0 ^ a_1
+// ^ a_2 ^ a_3) ^ a_r ^ key.  Rows are rewritten in order 0..3, so only the
+// column's total, a copy of row 0 (for row 3's a_(r+1)) and one row's
+// xtime input are live beside the state.
+template <bool KEY>
+__device__ __forceinline__ void bs_mix_col(uint32_t P[4][32], int c, uint32_t kw) {
+    uint32_t tot[8], a0[8];
 #pragma unroll
-    for (int c = 0; c < 4; c++) {
-        const uint32_t kw = rk[c];  // round-key word c holds rows 0..3 of column c
-        uint32_t t[4][8], tot[8];
+    for (int k = 0; k < 8; k++) {
+        a0[k] = PL(P, 4 * c, k);
+        tot[k] = __builtin_amdgcn_bitop3_b32(PL(P, 4 * c, k), PL(P, 4 * c + 1, k),
+                                             PL(P, 4 * c + 2, k), 0x96) ^
+                 PL(P, 4 * c + 3, k);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        uint32_t t[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            t[k] = PL(P, 4 * c + r, k) ^ (r == 3 ? a0[k] : PL(P, 4 * c + r + 1, k));
 #pragma unroll
         for (int k = 0; k < 8; k++) {
-#pragma unroll
-            for (int r = 0; r < 4; r++)
-                t[r][k] = PL(P, 4 * c + r, k) ^ PL(P, 4 * c + ((r + 1) & 3), k);
-            tot[k] = t[0][k] ^ t[2][k];
-        }
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-#pragma unroll
-            for (int k = 0; k < 8; k++) {
-                // xtime(t)_k = t_(k-1), with t_7 also fed into bits 0, 1, 3 and 4
-                const uint32_t xt = k == 0 ? t[r][7] : t[r][k - 1];
-                uint32_t v = __builtin_amdgcn_bitop3_b32(xt, tot[k], PL(P, 4 * c + r, k), 0x96);
-                const uint32_t km = key_mask(kw, 8 * r + k);
-                if (k == 1 || k == 3 || k == 4)
-                    v = __builtin_amdgcn_bitop3_b32(v, t[r][7], km, 0x96);
-                else
-                    v ^= km;
-                PL(P, 4 * c + r, k) = v;
-            }
+            // xtime(t)_k = t_(k-1), with t_7 also fed into bits 0, 1, 3 and 4
+            const uint32_t xt = k == 0 ? t[7] : t[k - 1];
+            uint32_t v = __builtin_amdgcn_bitop3_b32(xt, tot[k], PL(P, 4 * c + r, k), 0x96);
+            const uint32_t km = KEY ? key_mask(kw, 8 * r + k) : 0u;
+            if (k == 1 || k == 3 || k == 4)
+                v = KEY ? __builtin_amdgcn_bitop3_b32(v, t[7], km, 0x96) : v ^ t[7];
+            else if (KEY)
+                v ^= km;
+            PL(P, 4 * c + r, k) = v;
         }
     }
+}
+
+// MixColumns and AddRoundKey (FIPS-197 5.1.3-5.1.4), in place, column by
+// column (round-key word c holds rows 0..3 of column c).
+__device__ __forceinline__ void bs_mix_key(uint32_t P[4][32], const uint32_t *__restrict__ rk) {
+#pragma unroll
+    for (int c = 0; c < 4; c++)
+        bs_mix_col<true>(P, c, rk[c]);
 }
 
 // The cipher (FIPS-197 5.1) on 32 bitsliced blocks; nr = 10, 12 or 14.
@@ -148,6 +164,93 @@ __device__ __forceinline__ void bs_cipher(uint32_t P[4][32], const uint32_t *__r
     bs_sub_bytes(P);
     bs_shift_rows(P);
     bs_add_round_key(P, rk + 4 * nr);
+}
+
+// ---------------------------------------------------------- inverse cipher
+
+// InvShiftRows (FIPS-197 5.3.1): row r of the state rotates right by r
+// columns (the moves of bs_shift_rows reversed).
+__device__ __forceinline__ void bs_inv_shift_rows(uint32_t P[4][32]) {
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        uint32_t t = PL(P, 13, k);  // row 1: one column to the right
+        PL(P, 13, k) = PL(P, 9, k);
+        PL(P, 9, k) = PL(P, 5, k);
+        PL(P, 5, k) = PL(P, 1, k);
+        PL(P, 1, k) = t;
+        t = PL(P, 2, k);  // row 2: two columns
+        PL(P, 2, k) = PL(P, 10, k);
+        PL(P, 10, k) = t;
+        t = PL(P, 6, k);
+        PL(P, 6, k) = PL(P, 14, k);
+        PL(P, 14, k) = t;
+        t = PL(P, 3, k);  // row 3: three columns to the right (one to the left)
+        PL(P, 3, k) = PL(P, 7, k);
+        PL(P, 7, k) = PL(P, 11, k);
+        PL(P, 11, k) = PL(P, 15, k);
+        PL(P, 15, k) = t;
+    }
+}
+
+__device__ __forceinline__ void bs_inv_sub_bytes(uint32_t P[4][32]) {
+#pragma unroll
+    for (int b = 0; b < 16; b++)
+        bitslice_inv_sbox(PL(P, b, 0), PL(P, b, 1), PL(P, b, 2), PL(P, b, 3), PL(P, b, 4),
+                          PL(P, b, 5), PL(P, b, 6), PL(P, b, 7), PL(P, b, 0), PL(P, b, 1),
+                          PL(P, b, 2), PL(P, b, 3), PL(P, b, 4), PL(P, b, 5), PL(P, b, 6),
+                          PL(P, b, 7));
+}
+
+// {04} * t on one byte's planes: two xtime steps, each moving bit k to k + 1
+// and feeding bit 7 back into bits 0, 1, 3 and 4.
+__device__ __forceinline__ void bs_times4(const uint32_t t[8], uint32_t o[8]) {
+    o[0] = t[6];
+    o[1] = t[6] ^ t[7];
+    o[2] = t[0] ^ t[7];
+    o[3] = t[1] ^ t[6];
+    o[4] = __builtin_amdgcn_bitop3_b32(t[2], t[6], t[7], 0x96);
+    o[5] = t[3] ^ t[7];
+    o[6] = t[4];
+    o[7] = t[5];
+}
+
+// InvMixColumns (FIPS-197 5.3.3), in place: per column, a_r ^= {04}(a_r ^
+// a_(r+2)), then MixColumns.
+__device__ __forceinline__ void bs_inv_mix_columns(uint32_t P[4][32]) {
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+#pragma unroll
+        for (int r = 0; r < 2; r++) {
+            uint32_t d[8], u[8];
+#pragma unroll
+            for (int k = 0; k < 8; k++)
+                d[k] = PL(P, 4 * c + r, k) ^ PL(P, 4 * c + r + 2, k);
+            bs_times4(d, u);
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                PL(P, 4 * c + r, k) ^= u[k];
+                PL(P, 4 * c + r + 2, k) ^= u[k];
+            }
+        }
+        bs_mix_col<false>(P, c, 0u);
+    }
+}
+
+// The inverse cipher (FIPS-197 5.3, the straightforward form with the
+// encryption schedule, round keys taken from the last): nr = 10, 12 or 14.
+__device__ __forceinline__ void bs_inv_cipher(uint32_t P[4][32], const uint32_t *__restrict__ rk,
+                                              uint32_t nr) {
+    bs_add_round_key(P, rk + 4 * nr);
+#pragma unroll 1
+    for (uint32_t r = nr - 1; r >= 1; r--) {
+        bs_inv_shift_rows(P);
+        bs_inv_sub_bytes(P);
+        bs_add_round_key(P, rk + 4 * r);
+        bs_inv_mix_columns(P);
+    }
+    bs_inv_shift_rows(P);
+    bs_inv_sub_bytes(P);
+    bs_add_round_key(P, rk);
 }
 
 // Keystream of the 32 counter blocks ctr + 8 j + sub (j = 0..31) of one lane:

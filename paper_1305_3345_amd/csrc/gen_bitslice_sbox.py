@@ -1,6 +1,7 @@
 #!/usr/bin/env python3
-"""Generates bitslice_sbox.h: the AES S-box (FIPS-197 5.1.1) as a straight-line
-Boolean circuit for the bitsliced kernels, derived here in a tower field.
+"""Generates bitslice_sbox.h: the AES S-box and inverse S-box (FIPS-197 5.1.1,
+5.3.2) as straight-line Boolean circuits for the bitsliced kernels, derived
+here in a tower field.
 
 The multiplicative inverse in GF(2^8) = GF(2)[x]/(x^8+x^4+x^3+x+1) is computed
 in the isomorphic composite field GF((2^4)^2): GF(16) = GF(2)[y]/(y^4+y+1),
@@ -9,13 +10,16 @@ irreducible.  For a = hX + l:
     d = lam*h^2 + h*l + l^2,   a^-1 = (h*d^-1) X + ((h+l)*d^-1).
 The change of basis maps x -> b, where b is a root of the AES polynomial in the
 composite field (found by search); the output basis change is merged with the
-S-box affine map.  Linear maps are emitted as XOR networks (greedy pair
+S-box affine map.  The inverse S-box runs the same inversion between the inverse
+affine map (merged with the input basis change, its constant 0x63 included)
+and the plain output basis change.  Linear maps are emitted as XOR networks (greedy pair
 sharing), GF(16) products as AND/XOR terms, and d^-1 (four 4-input functions)
 by Shannon expansion into three-input lookups, which the kernel evaluates
 with v_bitop3_b32.
 
-The script checks the emitted circuit on all 256 inputs against an S-box it
-computes directly (inverse by search, then the affine map) before writing.
+The script checks the emitted circuits on all 256 inputs against an S-box it
+computes directly (inverse by search, then the affine map) and against that
+S-box's inverse permutation before writing.
 
 Run: python gen_bitslice_sbox.py   (rewrites bitslice_sbox.h beside it)
 """
@@ -138,6 +142,19 @@ def sbox_direct(a):
     return affine(inv)
 
 
+# The linear part of the affine map and its inverse (columns).
+AFF_COLS = [affine(1 << i) ^ 0x63 for i in range(8)]
+AFF_INV_COLS = invert_matrix(AFF_COLS)
+
+
+def apply_cols(cols, a):
+    r = 0
+    for i in range(8):
+        if (a >> i) & 1:
+            r ^= cols[i]
+    return r
+
+
 # Sanity: the map is a field isomorphism and the tower inverse is right.
 for a in range(256):
     for b in range(0, 256, 37):
@@ -230,10 +247,18 @@ def gf16_linear_rows(f):
     return [sum(((cols[i] >> r) & 1) << i for i in range(4)) for r in range(4)]
 
 
-def build():
+def build(inverse=False):
+    """The S-box circuit, or with inverse=True the inverse S-box circuit."""
     c = Circuit()
     u = [f"u{i}" for i in range(8)]
-    v = linear(c, u, [sum(((M_COLS[i] >> r) & 1) << i for i in range(8)) for r in range(8)])
+    if inverse:
+        # x = affine^-1(u) = L^-1(u) ^ L^-1(0x63), then into the composite basis
+        cols = [to_comp(AFF_INV_COLS[i]) for i in range(8)]
+        const = to_comp(apply_cols(AFF_INV_COLS, 0x63))
+        v = linear(c, u, [sum(((cols[i] >> r) & 1) << i for i in range(8)) for r in range(8)],
+                   consts=const)
+    else:
+        v = linear(c, u, [sum(((M_COLS[i] >> r) & 1) << i for i in range(8)) for r in range(8)])
     l, h = v[0:4], v[4:8]
     # lam*h^2 + l^2 (linear in h and l) plus h*l
     lin_h = gf16_linear_rows(lambda x: gf16_mul(LAM, gf16_mul(x, x)))
@@ -254,10 +279,16 @@ def build():
     hx = [c.op("xor2", h[i], l[i]) for i in range(4)]
     oh = gf16_mult(c, h, di)
     ol = gf16_mult(c, hx, di)
-    # output: affine(from_comp(oh:ol)) -- linear part and constant 0x63
-    lin_out = [affine(from_comp(1 << i)) ^ 0x63 for i in range(8)]
-    rows = [sum(((lin_out[i] >> r) & 1) << i for i in range(8)) for r in range(8)]
-    y = linear(c, ol + oh, rows, consts=0x63)
+    if inverse:
+        # output: from_comp(oh:ol)
+        lin_out = [from_comp(1 << i) for i in range(8)]
+        rows = [sum(((lin_out[i] >> r) & 1) << i for i in range(8)) for r in range(8)]
+        y = linear(c, ol + oh, rows)
+    else:
+        # output: affine(from_comp(oh:ol)) -- linear part and constant 0x63
+        lin_out = [affine(from_comp(1 << i)) ^ 0x63 for i in range(8)]
+        rows = [sum(((lin_out[i] >> r) & 1) << i for i in range(8)) for r in range(8)]
+        y = linear(c, ol + oh, rows, consts=0x63)
     return c, y
 
 
@@ -319,40 +350,54 @@ def emit(c, outs):
     return lines
 
 
+def function(name, what, c, outs):
+    body = emit(c, outs)
+    return (f"""// {what}: {len(c.ops)} operations.
+__device__ __forceinline__ void {name}(uint32_t u0, uint32_t u1, uint32_t u2,
+""" + " " * (len(name) + 33) + """uint32_t u3, uint32_t u4, uint32_t u5,
+""" + " " * (len(name) + 33) + """uint32_t u6, uint32_t u7, uint32_t &s0,
+""" + " " * (len(name) + 33) + """uint32_t &s1, uint32_t &s2, uint32_t &s3,
+""" + " " * (len(name) + 33) + """uint32_t &s4, uint32_t &s5, uint32_t &s6,
+""" + " " * (len(name) + 33) + """uint32_t &s7) {
+""" + "\n".join(body) + "\n}\n")
+
+
 def main():
     c, outs = build()
+    ci, outs_i = build(inverse=True)
+    sbox = [sbox_direct(a) for a in range(256)]
+    assert sorted(sbox) == list(range(256))
+    inv = [0] * 256
     for a in range(256):
-        assert simulate(c, outs, a) == sbox_direct(a), a
+        inv[sbox[a]] = a
+    for a in range(256):
+        assert simulate(c, outs, a) == sbox[a], a
+        assert simulate(ci, outs_i, a) == inv[a], a
     # the and-xor and mux tables follow the index convention above
     assert all(lut3_tt(x, y, z, 0x6A) == ((x & y) ^ z) for x in (0, 1) for y in (0, 1)
                for z in (0, 1))
     assert all(lut3_tt(x, y, z, 0xCA) == (y if x else z) for x in (0, 1) for y in (0, 1)
                for z in (0, 1))
-    body = emit(c, outs)
-    n_ops = len(c.ops)
     hdr = f"""// bitslice_sbox.h -- generated by gen_bitslice_sbox.py; do not edit.
 //
-// The AES S-box (FIPS-197 5.1.1) as a straight-line circuit on bit planes:
-// bit i of each input byte is in u<i> (one bit per lane bit, so 32 blocks at
-// once), the S-box output bit i is written to s<i>.  Derived in the tower
-// field GF((2^4)^2) with GF(16) = GF(2)[y]/(y^4+y+1) and X^2 + X + {LAM}
-// (root of the AES polynomial: 0x{BETA:02X} in that field); {n_ops} operations,
-// each one VALU instruction (three-input functions use v_bitop3_b32 with
-// index (S0 << 2) | (S1 << 1) | S2).  Checked on all 256 inputs when generated.
+// The AES S-box and inverse S-box (FIPS-197 5.1.1, 5.3.2) as straight-line
+// circuits on bit planes: bit i of each input byte is in u<i> (one bit per
+// lane bit, so 32 blocks at once), output bit i is written to s<i>.  Derived
+// in the tower field GF((2^4)^2) with GF(16) = GF(2)[y]/(y^4+y+1) and
+// X^2 + X + {LAM} (root of the AES polynomial: 0x{BETA:02X} in that field); each
+// operation is one VALU instruction (three-input functions use v_bitop3_b32
+// with index (S0 << 2) | (S1 << 1) | S2).  Both checked on all 256 inputs
+// when generated.
 #pragma once
 
 #include <stdint.h>
 
-__device__ __forceinline__ void bitslice_sbox(uint32_t u0, uint32_t u1, uint32_t u2,
-                                              uint32_t u3, uint32_t u4, uint32_t u5,
-                                              uint32_t u6, uint32_t u7, uint32_t &s0,
-                                              uint32_t &s1, uint32_t &s2, uint32_t &s3,
-                                              uint32_t &s4, uint32_t &s5, uint32_t &s6,
-                                              uint32_t &s7) {{
-""" + "\n".join(body) + "\n}\n"
+"""
+    text = hdr + function("bitslice_sbox", "S-box", c, outs) + "\n" + \
+        function("bitslice_inv_sbox", "Inverse S-box", ci, outs_i)
     with open(OUT, "w") as f:
-        f.write(hdr)
-    print(f"wrote {OUT}: {n_ops} ops, lambda={LAM}, beta=0x{BETA:02X}")
+        f.write(text)
+    print(f"wrote {OUT}: {len(c.ops)} + {len(ci.ops)} ops, lambda={LAM}, beta=0x{BETA:02X}")
 
 
 if __name__ == "__main__":

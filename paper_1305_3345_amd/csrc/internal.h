@@ -83,6 +83,11 @@ int launch_ctr_tiles(const Unit *d_units, uint32_t n_units, const aes_schedule_t
 int launch_ctr_bitslice(const Unit *d_units, uint32_t n_units, const aes_schedule_t *d_sched,
                         uint32_t n_sched, const uint8_t *d_in, uint8_t *d_out, int n_cu,
                         void *stream);
+// Bitsliced CBC and ECB decryption (aes_bitslice.hip): units in groups of 8
+// per wave, worked in 4 KiB chunks; d_preds as for launch_cbcdec_tiles.
+int launch_dec_bitslice(const Unit *d_units, uint32_t n_units, const aes_schedule_t *d_sched,
+                        uint32_t n_sched, const void *d_preds, const uint8_t *d_in,
+                        uint8_t *d_out, void *stream);
 // d_preds: NULL, or one 16-byte predecessor per unit written by
 // launch_snapshot_preds (used for FLAG_PRED_IN units instead of reading d_in).
 int launch_cbcdec_tiles(const Unit *d_units, uint32_t n_units, const aes_schedule_t *d_sched,

@@ -317,7 +317,11 @@ def test_launch_config_validation(ag, hctx):
     hctx.set_config(ctr_variant=ag.AES_CTR_BITSLICE, tile_bytes=8192)
     got = hctx.get_config()
     assert got["ctr_variant"] == ag.AES_CTR_BITSLICE and got["tile_bytes"] == 8192
-    for bad in ({"ctr_variant": 2}, {"chain_quad": 2}, {"tile_bytes": 1000}, {"ctr_nb": 3},
+    hctx.set_config(dec_variant=ag.AES_DEC_BITSLICE)
+    assert hctx.get_config()["dec_variant"] == ag.AES_DEC_BITSLICE
+    got = hctx.get_config()
+    for bad in ({"ctr_variant": 2}, {"dec_variant": 2}, {"chain_quad": 2}, {"tile_bytes": 1000},
+                {"ctr_nb": 3},
                 {"chain_lanes": 0},
                 {"mixed_nb": 4}, {"fuse": 2}):
         with pytest.raises(ag.AesError) as e:
@@ -354,6 +358,43 @@ def test_plan_orders_encryption_tiles(ag, hctx, spread, variant):
     plan.close()
     op = (units["meta"] >> 24) & 7
     assert np.flatnonzero(op == ag.AES_OP_CTR).max() < np.flatnonzero(op == ag.AES_OP_ECB_ENC).min()
+
+
+@pytest.mark.parametrize("variant", ["table", "bitslice"])
+@pytest.mark.parametrize("spread", [8, 200000])
+def test_plan_orders_decryption_tiles(ag, hctx, spread, variant):
+    """CBC- and ECB-decrypt tiles: in request order under the table variant;
+    grouped by key (ascending, request order kept within a key) under the
+    bitsliced decryption variant; snapshots flags and IVs as always."""
+    r = np.random.default_rng(spread + 1)
+    n = 120
+    reqs = np.zeros(n, workloads.REQ_DTYPE)
+    reqs["length"] = r.integers(1, 5, n) * 4096
+    reqs["offset"][1:] = np.cumsum(reqs["length"])[:-1]
+    reqs["op"] = np.where(r.random(n) < 0.3, ag.AES_OP_ECB_DEC, ag.AES_OP_CBC_DEC)
+    keys = r.choice(spread, min(spread, 10), replace=False)
+    reqs["key_idx"] = keys[r.integers(0, keys.size, n)]
+    reqs["iv"] = gen.bytes_(spread, 2, 16 * n).reshape(n, 16)
+    reqs = reqs[r.permutation(n)]
+    v = ag.AES_DEC_BITSLICE if variant == "bitslice" else ag.AES_DEC_TABLE
+    hctx.set_config(dec_variant=v)
+    plan = ag.Plan(hctx, reqs, int(keys.max()) + 1, int(reqs["offset"].max() + 4 * 4096))
+    _check_plan(ag, plan, reqs, 4096)
+    units = plan.units()
+    info = plan.info()
+    plan.close()
+    dec = units[:info["n_units_cbc_dec"]]
+    order = np.argsort(reqs["offset"], kind="stable")
+    pos = np.searchsorted(reqs["offset"][order], dec["offset"], side="right") - 1
+    req_of = order[pos].astype(np.int64)
+    key_of = (dec["meta"] & 0xFFFFFF).astype(np.int64)
+    if variant == "bitslice":
+        assert (np.diff(key_of) >= 0).all()
+        for key in np.unique(key_of):
+            mine = req_of[key_of == key]
+            assert (np.diff(mine) >= 0).all()
+    else:
+        assert (np.diff(req_of) >= 0).all()
 
 
 def _status(fn, *a, **k):

@@ -44,7 +44,7 @@ def raw_tune(ag, ctx, reqs, n_scheds=16, buf=1 << 30):
     best = np.zeros(1, ag.CONFIG_DTYPE)
     st = ag.lib().aes_tune(ctx.handle, reqs.ctypes.data, reqs.size, n_scheds, buf, D_SCHED,
                            D_IN, D_OUT, 1, best.ctypes.data)
-    return st, {k: int(best[0][k]) for k in FIELDS}
+    return st, {k: int(best[0][k]) for k in ag.CONFIG_DTYPE.names if k != "reserved"}
 
 
 def entry(sig, cfg):
@@ -91,6 +91,21 @@ def test_cache_hit_applies_config(ag, hctx, tmp_path, monkeypatch):
     assert got == want                      # the last complete entry of the signature
     assert hctx.get_config() == want         # and set in the context
     assert "not an entry" in path.read_text()  # a hit does not rewrite the file
+
+
+def test_cache_hit_keeps_decryption_variant(ag, hctx, tmp_path, monkeypatch):
+    """The cache holds the twelve tuned knobs; the context's decryption
+    variant (not tuned) stays as the caller set it across a hit."""
+    reqs = pages_reqs()
+    sig = ag.tune_key(hctx, reqs, 16)
+    hctx.set_config(dec_variant=ag.AES_DEC_BITSLICE)
+    want = dict(hctx.get_config(), tile_bytes=8192)
+    path = tmp_path / "tune.txt"
+    path.write_text(entry(sig, want) + "\n")
+    monkeypatch.setenv("AESGPU_TUNE_CACHE", str(path))
+    st, got = raw_tune(ag, hctx, reqs)
+    assert st == ag.AES_OK and got == want
+    assert hctx.get_config()["dec_variant"] == ag.AES_DEC_BITSLICE
 
 
 def test_cache_miss_and_unsupported_entry(ag, hctx, tmp_path, monkeypatch):
