@@ -593,7 +593,9 @@ def bench_serving(dev, n_measure=2000, n_warm=200):
         gpu = (m["gpu_done_ticks"].astype(np.int64) - m["gpu_dispatch_ticks"].astype(np.int64))
         if gpu.any():  # persistent engine: device clock, 100 MHz, dispatch -> last unit done
             for op, nm in ((workloads.OP_CBC_ENC, "enc"), (workloads.OP_CBC_DEC, "dec")):
-                out[f"{nm}_gpu_p50_us"] = round(float(np.percentile(gpu[ops == op], 50)) / 100, 1)
+                for q in (50, 99, 99.9):
+                    out[f"{nm}_gpu_p{str(q).replace('.', '')}_us"] = round(
+                        float(np.percentile(gpu[ops == op], q)) / 100, 1)
         return out
 
     burst = np.zeros(n)
