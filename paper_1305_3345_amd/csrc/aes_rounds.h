@@ -774,26 +774,58 @@ __device__ __forceinline__ void chain_quad_run(const uint32_t *lds, uint32_t L0,
     const uint32_t nblk = un.nbytes >> 4;
     const uint32_t *src = reinterpret_cast<const uint32_t *>(in + un.off) + q;
     uint32_t *dst = reinterpret_cast<uint32_t *>(out + un.off) + q;
-    constexpr uint32_t PF = 8;  // blocks fetched together
+    // Blocks go in groups of PF, software-pipelined: group g's words are
+    // loaded while group g-1's rounds run, and group g-1's ciphertext is
+    // stored while group g's run, so no wait falls on a load or store issued
+    // less than a group earlier (waiting on the loads of the group about to
+    // run cost about a seventh of a chain's time).
+    constexpr uint32_t PF = 8;
+    if (nblk == 0)
+        return;
+    uint32_t x[PF], y[PF];
+#pragma unroll
+    for (uint32_t j = 0; j < PF; j++)
+        x[j] = j < nblk ? src[4 * j] : 0u;
     for (uint32_t b = 0; b < nblk; b += PF) {
-        uint32_t x[PF];
+        // Using the group's first word here (an empty asm with a memory
+        // clobber keeps it in place) puts the wait for the group's loads
+        // before the stores and loads issued below.
+        uint32_t st = x[0] ^ prev ^ rk[0];
+        asm volatile("" ::"v"(st) : "memory");
+        // the previous group's ciphertext (every block of it exists), then
+        // the next group's words
+        if (b) {
+#pragma unroll
+            for (uint32_t j = 0; j < PF; j++)
+                dst[4 * (b - PF + j)] = y[j];
+        }
+        uint32_t xn[PF];
 #pragma unroll
         for (uint32_t j = 0; j < PF; j++)
-            x[j] = b + j < nblk ? src[4 * (b + j)] : 0u;
+            xn[j] = b + PF + j < nblk ? src[4 * (b + PF + j)] : 0u;
 #pragma unroll
         for (uint32_t j = 0; j < PF; j++) {
             if (b + j < nblk) {
-                uint32_t st = x[j] ^ prev ^ rk[0];
+                if (j)
+                    st = x[j] ^ prev ^ rk[0];
 #pragma unroll
                 for (int r = 1; r < MAXNR; r++) {
                     if (r < 10 || (uint32_t)r < nr)
                         st = quad_round_col(lds, st, rk[r], L0);
                 }
                 prev = quad_sub_col(lds, st, L0) ^ rkl;
-                dst[4 * (b + j)] = prev;
+                y[j] = prev;
             }
         }
+#pragma unroll
+        for (uint32_t j = 0; j < PF; j++)
+            x[j] = xn[j];
     }
+    const uint32_t bl = (nblk - 1u) / PF * PF;
+#pragma unroll
+    for (uint32_t j = 0; j < PF; j++)
+        if (bl + j < nblk)
+            dst[4 * (bl + j)] = y[j];
 }
 
 // Key check and round-count dispatch for the chains of a wave's quads (un,
