@@ -75,6 +75,9 @@ def parse():
     ap.add_argument("--skip-lds-probe", action="store_true",
                     help="leave out the LDS gather probe (its ceiling is then null); for "
                          "profiler runs, which would also profile the probe's process")
+    ap.add_argument("--skip-beside-server", action="store_true",
+                    help="skip the batch launch timed beside a live persistent server (it waits "
+                         "out the server's idle timeout, about 1 s per launch)")
     ap.add_argument("--skip-host-serving", action="store_true",
                     help="skip serving with payloads in pinned host memory")
     ap.add_argument("--skip-variants", action="store_true",
@@ -975,7 +978,7 @@ def main():
         serving = bench_serving(dev, n_measure=args.serve_requests, n_warm=args.serve_warmup)
 
     beside = None
-    if not args.skip_serving:
+    if not args.skip_serving and not args.skip_beside_server:
         beside = bench_beside_server(dev, n_pages)
 
     host_serving = None
