@@ -423,9 +423,12 @@ typedef struct aes_server_config {
     uint32_t ring_slots;        /* power of two, 64..65536 (default 4096) */
     uint32_t key_slots;         /* resident key schedules, 1..65536 (default 256) */
     uint32_t n_workgroups;      /* persistent grid of 512-thread workgroups, each holding a
-                                   whole compute unit's LDS; 0 = compute units minus 16; at
-                                   most the workgroups the device holds at once (the compute
-                                   units), else AES_ERR_ARG.  1 = one workgroup with the
+                                   whole compute unit's LDS; 0 = seven eighths of the compute
+                                   units (224 of 256); at most the workgroups the device holds
+                                   at once (the compute units), else AES_ERR_ARG.  A grid that
+                                   fills a shader engine (above 224 on a 256-CU device) holds
+                                   back every kernel launched on the device beside it until
+                                   the persistent kernel exits.  1 = one workgroup with the
                                    encryption tables only (CTR, ECB and CBC encryption in the
                                    kernel; decryption requests take a normal launch) */
     uint32_t dec_workgroups;    /* of those, workgroups holding decryption tables; 0 = half;

@@ -456,3 +456,36 @@ def test_unloaded_key_slot(ctx, engine):
     for r in wl.reqs:
         o, n = int(r["offset"]), int(r["length"])
         assert first_mismatch(got[o:o + n], oracle_request(wl, r, inp[o:o + n])) is None
+
+
+def test_batch_runs_beside_default_persistent_grid(ctx):
+    """A batch launch issued while a persistent kernel of the default grid is
+    live runs beside it (on the compute units the grid leaves free) instead
+    of waiting for the kernel's idle exit; its bytes equal the oracle's.  The
+    idle timeout is 10 s, so a launch held back until the exit would take
+    that long; the bound here is 3 s."""
+    print("[gpu] batch launch beside a live default persistent grid", flush=True)
+    a = ag()
+    wl = workloads.config2(workloads.OP_CTR, 128, n_pages=16384)
+    inp = wl.data()
+    d_in = torch.from_numpy(inp).cuda()
+    d_out = torch.from_numpy(workloads.sentinel(inp.size)).cuda()
+    scheds = a.expand_keys(wl.keys, wl.key_bits)
+    d_s = a.schedules_to_device(scheds, torch.device("cuda:0"))
+    plan = a.Plan(ctx, wl.reqs, wl.keys.shape[0], wl.buf_bytes)
+    small = torch.zeros(4096, dtype=torch.uint8, device="cuda")
+    sync()
+    with a.Server(ctx, mode=a.AES_SERVE_PERSISTENT, key_slots=1, idle_timeout_ms=10000) as srv:
+        srv.set_key(0, scheds[0])
+        done = srv.wait(srv.submit(workloads.OP_CTR, 0, bytes(16), small, small, 4096))
+        assert done["status"] == 0
+        t0 = time.perf_counter()
+        plan.launch(d_s, d_in, d_out)
+        sync()
+        took = time.perf_counter() - t0
+    plan.close()
+    assert took < 3.0, f"the batch launch waited {took:.2f} s beside the persistent kernel"
+    want = workloads.sentinel(inp.size)
+    oracle.batch(inp, want, wl.reqs, wl.keys, wl.key_bits, n_threads=0)
+    msg = first_mismatch(d_out.cpu().numpy(), want)
+    assert msg is None, msg
