@@ -479,7 +479,9 @@ int aes_server_create(aes_ctx_t *ctx, const aes_server_config_t *cfg, aes_server
 /* Copies a schedule into resident slot `slot` (synchronously).  Allowed while
  * nothing is in flight (else AES_ERR_STATE); a running persistent kernel is
  * stopped first (AES_ERR_TIMEOUT if it does not exit within 10 s) and
- * relaunched by the next submit. */
+ * relaunched by the next submit.  The schedule's round count must match its
+ * key size (10, 12, 14 for 128, 192, 256 bits), else AES_ERR_KEYSIZE: the
+ * persistent engine takes the round count recorded here with each request. */
 int aes_server_set_key(aes_server_t *srv, uint32_t slot, const aes_schedule_t *host_sched);
 /* Posts one request (paper section 3.2: buffers, a service request, an
  * optional completion callback).  op and iv as in aes_req_t (iv may be NULL

@@ -66,7 +66,7 @@ struct ServeDesc {
     uint32_t length;
     uint32_t key_slot;
     uint32_t op;
-    uint32_t reserved;
+    uint32_t nr;  // the key slot's round count, recorded by the host at set_key
     uint32_t iv[4];
     uint64_t t_submit;
 };
@@ -90,9 +90,10 @@ struct ServeUnit {
     uint64_t dst;
     uint64_t pos;  // ring position of the request
     uint32_t slot;
-    uint32_t reserved;
+    uint32_t info;  // bits 0..7 the round count; UNIT_ONLY: the request's only unit
 };
 static_assert(sizeof(ServeUnit) == 64, "queue unit is 64 bytes");
+constexpr uint32_t UNIT_ONLY = 1u << 8;
 
 // Queue counters, each on its own 128-byte line.
 struct ServeQueue {
@@ -181,7 +182,8 @@ __device__ void dispatch_loop(const ServeArgs &a) {
             len = __hip_atomic_load(&d->length, __ATOMIC_RELAXED, SYS);
             const uint32_t key = __hip_atomic_load(&d->key_slot, __ATOMIC_RELAXED, SYS);
             const uint32_t op = __hip_atomic_load(&d->op, __ATOMIC_RELAXED, SYS);
-            misc = ((uint64_t)op << 32) | key;
+            const uint32_t nr = __hip_atomic_load(&d->nr, __ATOMIC_RELAXED, SYS);
+            misc = ((uint64_t)op << 32) | ((uint64_t)(nr & 0xFFu) << 24) | (key & 0xFFFFFFu);
             ivlo = (uint64_t)__hip_atomic_load(&d->iv[0], __ATOMIC_RELAXED, SYS) |
                    ((uint64_t)__hip_atomic_load(&d->iv[1], __ATOMIC_RELAXED, SYS) << 32);
             ivhi = (uint64_t)__hip_atomic_load(&d->iv[2], __ATOMIC_RELAXED, SYS) |
@@ -196,7 +198,8 @@ __device__ void dispatch_loop(const ServeArgs &a) {
             const uint64_t r_misc = __shfl(misc, (int)i);
             const uint64_t r_ivlo = __shfl(ivlo, (int)i);
             const uint64_t r_ivhi = __shfl(ivhi, (int)i);
-            const uint32_t key = (uint32_t)r_misc;
+            const uint32_t key = (uint32_t)r_misc & 0xFFFFFFu;
+            const uint32_t nr = ((uint32_t)r_misc >> 24) & 0xFFu;
             const uint32_t op = (uint32_t)(r_misc >> 32);
             const uint64_t t_disp = now_ticks();
             if (lane == 0)
@@ -215,6 +218,7 @@ __device__ void dispatch_loop(const ServeArgs &a) {
             // descriptor from reaching the kernels.
             const int qi = op == AES_OP_CBC_DEC || op == AES_OP_ECB_DEC ? 1 : 0;
             const bool ok = op <= AES_OP_ECB_DEC && key < a.n_keys && r_len > 0 &&
+                            (nr == 10 || nr == 12 || nr == 14) &&
                             r_len <= a.max_bytes && (op == AES_OP_CTR || (r_len & 15u) == 0) &&
                             r_src && r_dst && (qi == 0 || a.n_dec_wg > 0);
             if (!ok) {
@@ -263,7 +267,7 @@ __device__ void dispatch_loop(const ServeArgs &a) {
                 su.dst = r_dst;
                 su.pos = pos;
                 su.slot = slot;
-                su.reserved = 0;
+                su.info = nr | (k == 1u ? UNIT_ONLY : 0u);
                 a.qunits[qi][(tail[qi] + j) & a.qmask] = su;
             }
             tail[qi] += k;
@@ -309,18 +313,21 @@ __device__ __forceinline__ bool claim(const ServeArgs &a, int qi, uint64_t *idx)
     const uint64_t pos = ((uint64_t)hi << 32) | lo;
     uint32_t nap = 1;
     for (;;) {
-        if (pos < poll_u64(&q->tail))
-            break;
+        // the tail and the closed flag in one round trip
+        const uint64_t t = poll_u64(&q->tail);
         const uint32_t closed =
             __builtin_amdgcn_readfirstlane(__hip_atomic_load(a.closed, __ATOMIC_RELAXED, AGT));
+        if (pos < t)
+            break;
         if (closed) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             if (pos < poll_u64(&q->tail))
                 break;
             return false;
         }
-        // Back off from about 0.03 to 1 microsecond between polls.
-        if (nap < 16) {
+        // The waves holding the next four positions poll back to back; the
+        // others back off from about 0.03 to 1 microsecond between polls.
+        if (pos - t < 4u || nap < 16) {
             __builtin_amdgcn_s_sleep(1);
             nap++;
         } else {
@@ -330,6 +337,63 @@ __device__ __forceinline__ bool claim(const ServeArgs &a, int qi, uint64_t *idx)
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *idx = pos;
     return true;
+}
+
+// One queue unit.  Its round count comes with it (the host records each key
+// slot's at aes_server_set_key and the dispatcher copies it into the unit),
+// so the round keys and the unit's data are requested together instead of
+// after a load of the schedule's round count, one memory round trip fewer.
+template <bool DEC>
+__device__ __forceinline__ void serve_unit(const uint32_t *lds, uint32_t L0, uint32_t L2,
+                                           uint32_t lane, const Unit &un, uint32_t nr,
+                                           const ServeArgs &a, const uint8_t *src,
+                                           uint8_t *dst) {
+    const uint32_t key = un.meta & META_KEY_MASK;
+    if (key >= a.n_keys)
+        return;
+    const aes_schedule_t *ks = a.keys + key;
+    const uint32_t op = unit_op(un.meta);
+    if (DEC) {
+        if (op == AES_OP_ECB_DEC) {
+            if (nr == 10)
+                cbcdec_unit<1, 10, true>(lds, L0, L2, lane, un, nullptr, ks->dk, src, dst);
+            else if (nr == 12)
+                cbcdec_unit<1, 12, true>(lds, L0, L2, lane, un, nullptr, ks->dk, src, dst);
+            else if (nr == 14)
+                cbcdec_unit<1, 14, true>(lds, L0, L2, lane, un, nullptr, ks->dk, src, dst);
+        } else {
+            if (nr == 10)
+                cbcdec_unit<1, 10, false>(lds, L0, L2, lane, un, nullptr, ks->dk, src, dst);
+            else if (nr == 12)
+                cbcdec_unit<1, 12, false>(lds, L0, L2, lane, un, nullptr, ks->dk, src, dst);
+            else if (nr == 14)
+                cbcdec_unit<1, 14, false>(lds, L0, L2, lane, un, nullptr, ks->dk, src, dst);
+        }
+    } else if (op == AES_OP_CBC_ENC) {
+        // One serial chain, on four lanes (one state column each).
+        if (lane >= 4u)
+            return;
+        if (nr == 10)
+            chain_quad_run<10>(lds, L0, lane, un, ks->ek, nr, src, dst);
+        else if (nr == 12)
+            chain_quad_run<12>(lds, L0, lane, un, ks->ek, nr, src, dst);
+        else if (nr == 14)
+            chain_quad_run<14>(lds, L0, lane, un, ks->ek, nr, src, dst);
+    } else if (op == AES_OP_ECB_ENC) {
+        if (nr == 10)
+            ecb_enc_unit<1, 10>(lds, L0, lane, un, ks->ek, src, dst);
+        else if (nr == 12)
+            ecb_enc_unit<1, 12>(lds, L0, lane, un, ks->ek, src, dst);
+        else if (nr == 14)
+            ecb_enc_unit<1, 14>(lds, L0, lane, un, ks->ek, src, dst);
+    } else {
+        if (nr == 10)
+            ctr_unit<1, 10>(lds, L0, lane, un, ks->ek, src, dst);
+        else if (nr == 12)
+            ctr_unit<1, 12>(lds, L0, lane, un, ks->ek, src, dst);
+        else if (nr == 14)
+            ctr_unit<1, 14>(lds, L0, lane, un, ks->ek, src, dst);
+    }
 }
 
 template <bool DEC>
@@ -353,17 +417,17 @@ __device__ void worker_loop(const ServeArgs &a, const uint32_t *lds) {
         uint8_t *dst = (uint8_t *)__hip_atomic_load(&p->dst, __ATOMIC_RELAXED, AGT);
         const uint64_t pos = __hip_atomic_load(&p->pos, __ATOMIC_RELAXED, AGT);
         const uint32_t slot = __hip_atomic_load(&p->slot, __ATOMIC_RELAXED, AGT);
-        const uint32_t op = unit_op(un.meta);
-        if (DEC) {
-            run_dec_unit<1>(lds, L0, L2, lane, un, nullptr, a.keys, a.n_keys, src, dst);
-        } else if (op == AES_OP_CBC_ENC) {
-            // One serial chain, on four lanes (one state column each).
-            run_chain_quad(lds, L0, lane, un, a.keys, a.n_keys, src, dst);
-        } else {
-            run_ctr_unit<1>(lds, L0, lane, un, a.keys, a.n_keys, src, dst);
-        }
-        // Make this unit's output visible beyond the device, then count it.
+        const uint32_t info =
+            __builtin_amdgcn_readfirstlane(__hip_atomic_load(&p->info, __ATOMIC_RELAXED, AGT));
+        serve_unit<DEC>(lds, L0, L2, lane, un, info & 0xFFu, a, src, dst);
+        // Make this unit's output visible beyond the device, then count it
+        // (a request's only unit completes it without the count).
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+        if (info & UNIT_ONLY) {
+            if (lane == 0)
+                complete(a, slot, pos, AES_OK);
+            continue;
+        }
         uint32_t left = 0;
         if (lane == 0)
             left = __hip_atomic_fetch_sub(&a.remaining[slot], 1u, __ATOMIC_ACQ_REL, AGT);
@@ -814,7 +878,7 @@ int submit_locked(aes_server *s, uint32_t op, uint32_t key_slot, const uint8_t *
         d->length = (uint32_t)length;
         d->key_slot = key_slot;
         d->op = op;
-        d->reserved = 0;
+        d->nr = s->keys_h[key_slot].nr;
         if (iv)
             memcpy(d->iv, iv, 16);
         else
@@ -1102,6 +1166,10 @@ int aes_server_set_key(aes_server_t *s, uint32_t slot, const aes_schedule_t *hos
         return AES_ERR_ARG;
     if (slot >= s->cfg.key_slots)
         return AES_ERR_RANGE;
+    // The persistent engine takes the round count from here with each request.
+    const uint32_t kb = host_sched->key_bits, nr = host_sched->nr;
+    if (!((kb == 128 && nr == 10) || (kb == 192 && nr == 12) || (kb == 256 && nr == 14)))
+        return AES_ERR_KEYSIZE;
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->inflight)
         return AES_ERR_STATE;

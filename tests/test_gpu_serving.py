@@ -489,3 +489,20 @@ def test_batch_runs_beside_default_persistent_grid(ctx):
     oracle.batch(inp, want, wl.reqs, wl.keys, wl.key_bits, n_threads=0)
     msg = first_mismatch(d_out.cpu().numpy(), want)
     assert msg is None, msg
+
+
+def test_set_key_rejects_a_mismatched_round_count(ctx):
+    """aes_server_set_key refuses a schedule whose round count does not match
+    its key size (AES_ERR_KEYSIZE): the persistent engine takes the round
+    count recorded at set_key with every request."""
+    print("[gpu] set_key round-count check", flush=True)
+    a = ag()
+    keys, kb = workloads.make_keys(0, 1, 128)
+    sch = a.expand_keys(keys, kb)
+    bad = sch.copy()
+    bad["nr"] = 12
+    with a.Server(ctx, mode=a.AES_SERVE_PERSISTENT, key_slots=1) as srv:
+        with pytest.raises(a.AesError) as e:
+            srv.set_key(0, bad[0])
+        assert e.value.status == a.AES_ERR_KEYSIZE
+        srv.set_key(0, sch[0])
