@@ -828,8 +828,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU hot path "
-              "(pages shard across GPUs with no exchange; see the design notes).",
+        print("bench.py runs on one GPU only: it measures the single-GPU hot path "
+              "(the pages would shard across GPUs with no exchange between them).",
               file=sys.stderr)
         sys.exit(2)
 

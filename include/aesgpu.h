@@ -322,7 +322,7 @@ int aes_ctx_set_config(aes_ctx_t *ctx, const aes_launch_config_t *cfg);
  *
  * Tune cache: when the environment variable AESGPU_TUNE_CACHE names a file,
  * the batch's signature (aes_tune_key) is looked up there first; a stored
- * configuration that this build supports is set and returned without any
+ * configuration that the library supports is set and returned without any
  * launch (also on a host-only context).  Otherwise the tuner runs and stores
  * its result under the signature.  The file is text, one entry per line:
  * the signature, a TAB, and the twelve configuration fields tile_bytes ..

@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libaesgpu.so")
 # The LDS gather probe (a stand-alone program the benchmark runs to measure
-# the ceiling of the round-table kernels on the box it runs on).
+# the ceiling of the round-table kernels on the machine it runs on).
 PROBE_SRC = os.path.join(HERE, "probe", "lds_gather_probe.cpp")
 PROBE = os.path.join(HERE, "probe", "lds_gather_probe")
 

@@ -1555,7 +1555,7 @@ int aes_tune(aes_ctx_t *ctx, const aes_req_t *reqs, uint64_t n_reqs, uint32_t n_
     if ((st = validate(reqs, n_reqs, n_scheds, buf_bytes)))
         return st;
     // The tune cache: a stored configuration for a batch of this shape is
-    // applied without timing (if this build still supports it).
+    // applied without timing (if the library still supports it).
     const char *cache = getenv("AESGPU_TUNE_CACHE");
     std::string sig;
     if (cache && *cache) {
