@@ -3,6 +3,7 @@
 // tile_kernel.h, instantiated by aes_tiles_ctr.hip and aes_tiles_dec.hip.
 #include <hip/hip_runtime.h>
 
+#include "aes_chain.h"
 #include "aes_rounds.h"
 #include "internal.h"
 

@@ -52,6 +52,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "aes_chain.h"
 #include "aes_rounds.h"
 #include "internal.h"
 
