@@ -12,6 +12,10 @@
 
 namespace aesgpu {
 
+// A 32-bit word in global memory (device memory, or host memory mapped into
+// the device).
+typedef __attribute__((address_space(1))) uint32_t gu32;
+
 // ------------------------------------------------------- CBC-encrypt chains
 
 // SP 800-38A 6.2: C_j = E(P_j ^ C_(j-1)); one chain per lane, strictly serial.
@@ -175,8 +179,13 @@ __device__ __forceinline__ void chain_quad_run(const uint32_t *lds, uint32_t L0,
     for (uint32_t w = 0; w < 4; w++)
         prev |= un.w[w] & (0u - (uint32_t)(q == w));
     const uint32_t nblk = un.nbytes >> 4;
-    const uint32_t *src = reinterpret_cast<const uint32_t *>(in + un.off) + q;
-    uint32_t *dst = reinterpret_cast<uint32_t *>(out + un.off) + q;
+    // Through the global address space: a payload pointer that the compiler
+    // cannot trace to a kernel argument (the serving kernel reads it from a
+    // queue unit) would otherwise be accessed with flat instructions, which
+    // it also counts as LDS operations, and every round's LDS wait would then
+    // be for all four lookups instead of the next one.
+    const gu32 *src = (const gu32 *)(in + un.off) + q;
+    gu32 *dst = (gu32 *)(out + un.off) + q;
     // Blocks go in groups of PF, software-pipelined: group g's words are
     // loaded while group g-1's rounds run, and group g-1's ciphertext is
     // stored while group g's run, so no wait falls on a load or store issued
