@@ -272,9 +272,11 @@ __device__ void dispatch_loop(const ServeArgs &a) {
                 a.qunits[qi][(tail[qi] + j) & a.qmask] = su;
             }
             tail[qi] += k;
+            // The fence orders the unit records before the tail (a release
+            // store after it would write the cache back a second time).
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             if (lane == 0)
-                __hip_atomic_store(&a.q[qi].tail, tail[qi], __ATOMIC_RELEASE, AGT);
+                __hip_atomic_store(&a.q[qi].tail, tail[qi], __ATOMIC_RELAXED, AGT);
         }
         next += n_ready;
         if (lane == 0)
@@ -429,12 +431,17 @@ __device__ void worker_loop(const ServeArgs &a, const uint32_t *lds) {
                 complete(a, slot, pos, AES_OK);
             continue;
         }
+        // The release fence above orders this unit's output before the count;
+        // the last unit acquires the others' before completing the request.
         uint32_t left = 0;
         if (lane == 0)
-            left = __hip_atomic_fetch_sub(&a.remaining[slot], 1u, __ATOMIC_ACQ_REL, AGT);
+            left = __hip_atomic_fetch_sub(&a.remaining[slot], 1u, __ATOMIC_RELAXED, AGT);
         left = __builtin_amdgcn_readfirstlane(left);
-        if (left == 1u && lane == 0)
-            complete(a, slot, pos, AES_OK);
+        if (left == 1u) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (lane == 0)
+                complete(a, slot, pos, AES_OK);
+        }
     }
 }
 
