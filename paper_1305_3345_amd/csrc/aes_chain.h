@@ -160,9 +160,33 @@ __device__ __forceinline__ uint32_t quad_sub_col(const uint32_t *lds, uint32_t s
     return pick_diag(a, b, c, d);
 }
 
+// One block of a quad's chain: the whitened state st through rounds 1 ..
+// MAXNR-1 and the last round.  A quad whose schedule has fewer rounds than
+// MAXNR (quads of one wave may mix key sizes) runs the extra rounds too and
+// takes the state it had before them into its last round: a select instead of
+// a branch around each extra round, which costs two exec-mask updates and two
+// taken branches per round.  With nr == MAXNR known at compile time the
+// selects fold away.
+template <int MAXNR>
+__device__ __forceinline__ uint32_t quad_block(const uint32_t *lds, uint32_t st, const uint32_t *rk,
+                                               uint32_t rkl, uint32_t nr, uint32_t L0) {
+    uint32_t s10 = 0, s12 = 0;  // the state entering round 10 / round 12
+#pragma unroll
+    for (int r = 1; r < MAXNR; r++) {
+        if (r == 10)
+            s10 = st;
+        if (r == 12)
+            s12 = st;
+        st = quad_round_col(lds, st, rk[r], L0);
+    }
+    if (MAXNR > 10)
+        st = nr == 10u ? s10 : (MAXNR > 12 && nr == 12u ? s12 : st);
+    return quad_sub_col(lds, st, L0) ^ rkl;
+}
+
 // Runs a quad's chain.  Lanes of a quad share one chain (un, ek, nr); quads
 // of a wave may have different chains, keys and key sizes: rounds run up to
-// MAXNR, a quad with fewer rounds sits out the extra ones.
+// MAXNR.
 template <int MAXNR>
 __device__ __forceinline__ void chain_quad_run(const uint32_t *lds, uint32_t L0, uint32_t q,
                                                const Unit &un, const uint32_t *ek, uint32_t nr,
@@ -179,6 +203,8 @@ __device__ __forceinline__ void chain_quad_run(const uint32_t *lds, uint32_t L0,
     for (uint32_t w = 0; w < 4; w++)
         prev |= un.w[w] & (0u - (uint32_t)(q == w));
     const uint32_t nblk = un.nbytes >> 4;
+    if (nblk == 0)
+        return;
     // Through the global address space: a payload pointer that the compiler
     // cannot trace to a kernel argument (the serving kernel reads it from a
     // queue unit) would otherwise be accessed with flat instructions, which
@@ -190,54 +216,67 @@ __device__ __forceinline__ void chain_quad_run(const uint32_t *lds, uint32_t L0,
     // loaded while group g-1's rounds run, and group g-1's ciphertext is
     // stored while group g's run, so no wait falls on a load or store issued
     // less than a group earlier (waiting on the loads of the group about to
-    // run cost about a seventh of a chain's time).
+    // run cost about a seventh of a chain's time).  Loads past the chain's
+    // end read its last block again (always in bounds, and no branch); the
+    // whole groups run without per-block checks, a partial last group after
+    // them.
     constexpr uint32_t PF = 8;
-    if (nblk == 0)
-        return;
+    const uint32_t last = nblk - 1u;
+    const uint32_t nfull = nblk / PF * PF;
     uint32_t x[PF], y[PF];
 #pragma unroll
     for (uint32_t j = 0; j < PF; j++)
-        x[j] = j < nblk ? src[4 * j] : 0u;
-    for (uint32_t b = 0; b < nblk; b += PF) {
+        x[j] = src[4 * (j < last ? j : last)];
+    uint32_t b = 0;
+    for (; b < nfull; b += PF) {
         // Using the group's first word here (an empty asm with a memory
         // clobber keeps it in place) puts the wait for the group's loads
         // before the stores and loads issued below.
         uint32_t st = x[0] ^ prev ^ rk[0];
         asm volatile("" ::"v"(st) : "memory");
-        // the previous group's ciphertext (every block of it exists), then
-        // the next group's words
         if (b) {
+            gu32 *d = dst + 4 * (b - PF);
 #pragma unroll
             for (uint32_t j = 0; j < PF; j++)
-                dst[4 * (b - PF + j)] = y[j];
+                d[4 * j] = y[j];
         }
         uint32_t xn[PF];
 #pragma unroll
-        for (uint32_t j = 0; j < PF; j++)
-            xn[j] = b + PF + j < nblk ? src[4 * (b + PF + j)] : 0u;
+        for (uint32_t j = 0; j < PF; j++) {
+            const uint32_t i = b + PF + j;
+            xn[j] = src[4 * (i < last ? i : last)];
+        }
+        // Keeps the loads here, a group ahead of their use (without it the
+        // scheduler sinks them to the end of the group, next to the copies
+        // into x, and the group ends waiting on them).
+        asm volatile("" ::: "memory");
 #pragma unroll
         for (uint32_t j = 0; j < PF; j++) {
-            if (b + j < nblk) {
-                if (j)
-                    st = x[j] ^ prev ^ rk[0];
-#pragma unroll
-                for (int r = 1; r < MAXNR; r++) {
-                    if (r < 10 || (uint32_t)r < nr)
-                        st = quad_round_col(lds, st, rk[r], L0);
-                }
-                prev = quad_sub_col(lds, st, L0) ^ rkl;
-                y[j] = prev;
-            }
+            if (j)
+                st = x[j] ^ prev ^ rk[0];
+            prev = quad_block<MAXNR>(lds, st, rk, rkl, nr, L0);
+            y[j] = prev;
         }
 #pragma unroll
         for (uint32_t j = 0; j < PF; j++)
             x[j] = xn[j];
     }
-    const uint32_t bl = (nblk - 1u) / PF * PF;
+    if (nfull) {
+        gu32 *d = dst + 4 * (nfull - PF);
 #pragma unroll
-    for (uint32_t j = 0; j < PF; j++)
-        if (bl + j < nblk)
-            dst[4 * (bl + j)] = y[j];
+        for (uint32_t j = 0; j < PF; j++)
+            d[4 * j] = y[j];
+    }
+    if (nfull < nblk) {
+        gu32 *d = dst + 4 * nfull;
+#pragma unroll
+        for (uint32_t j = 0; j < PF - 1; j++) {
+            if (nfull + j < nblk) {
+                prev = quad_block<MAXNR>(lds, x[j] ^ prev ^ rk[0], rk, rkl, nr, L0);
+                d[4 * j] = prev;
+            }
+        }
+    }
 }
 
 // Key check and round-count dispatch for the chains of a wave's quads (un,
@@ -277,11 +316,11 @@ __device__ __forceinline__ void run_chain_quad(const uint32_t *lds, uint32_t L0,
     const aes_schedule_t *ks = sched + key;
     const uint32_t nr = ks->nr;
     if (nr == 10)
-        chain_quad_run<10>(lds, L0, lane, un, ks->ek, nr, in, out);
+        chain_quad_run<10>(lds, L0, lane, un, ks->ek, 10u, in, out);
     else if (nr == 12)
-        chain_quad_run<12>(lds, L0, lane, un, ks->ek, nr, in, out);
+        chain_quad_run<12>(lds, L0, lane, un, ks->ek, 12u, in, out);
     else if (nr == 14)
-        chain_quad_run<14>(lds, L0, lane, un, ks->ek, nr, in, out);
+        chain_quad_run<14>(lds, L0, lane, un, ks->ek, 14u, in, out);
 }
 
 // Chains of a wave in quads: 16 chains per wave, four lanes each.  Wave e

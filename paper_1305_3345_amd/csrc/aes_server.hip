@@ -377,11 +377,11 @@ __device__ __forceinline__ void serve_unit(const uint32_t *lds, uint32_t L0, uin
         if (lane >= 4u)
             return;
         if (nr == 10)
-            chain_quad_run<10>(lds, L0, lane, un, ks->ek, nr, src, dst);
+            chain_quad_run<10>(lds, L0, lane, un, ks->ek, 10u, src, dst);
         else if (nr == 12)
-            chain_quad_run<12>(lds, L0, lane, un, ks->ek, nr, src, dst);
+            chain_quad_run<12>(lds, L0, lane, un, ks->ek, 12u, src, dst);
         else if (nr == 14)
-            chain_quad_run<14>(lds, L0, lane, un, ks->ek, nr, src, dst);
+            chain_quad_run<14>(lds, L0, lane, un, ks->ek, 14u, src, dst);
     } else if (op == AES_OP_ECB_ENC) {
         if (nr == 10)
             ecb_enc_unit<1, 10>(lds, L0, lane, un, ks->ek, src, dst);
