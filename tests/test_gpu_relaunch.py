@@ -7,11 +7,12 @@ default grid, on a grid of 24 and one of 20 workgroups, with unit counts that
 do not divide evenly between them; single calls of varying sizes and both
 tile sides in turn on one stream; and in-place CBC decryption relaunched on
 its own output."""
+import numpy as np
 import pytest
 import torch
 
 from synth import workloads
-from tests.gpu_util import ag, device_schedules, first_mismatch, run_oracle
+from tests.gpu_util import ag, device_schedules, first_mismatch, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -101,3 +102,39 @@ def test_in_place_relaunched(fresh):
             check(d.cpu().numpy(), want, f"in-place launch {rep}")
     finally:
         plan.close()
+
+
+def small_requests(op, seed, n=300):
+    """n requests of 16 B to 4 KiB - 16 B (one unit each, shorter than a
+    tile's step for most tile shapes), packed back to back from offset 0 with
+    gaps of 16 to 31 bytes, keys of all three sizes."""
+    rng = np.random.default_rng(seed)
+    lengths = (rng.integers(1, 256, n) * 16).astype(np.uint64)
+    if op == workloads.OP_CTR:
+        lengths -= (np.arange(n) % 16).astype(np.uint64)  # ragged CTR lengths
+        lengths[lengths == 0] = 1
+    reqs = np.zeros(n, workloads.REQ_DTYPE)
+    reqs["length"] = lengths
+    reqs["offset"][1:] = np.cumsum((lengths + 31) // 16 * 16)[:-1]
+    reqs["op"] = op
+    reqs["key_idx"] = np.arange(n) % 3
+    reqs["iv"] = rng.integers(0, 256, (n, 16), dtype=np.uint8)
+    keys, kb = workloads.make_keys(seed, 3, [128, 192, 256])
+    buf = int(reqs["offset"][-1] + reqs["length"][-1] + 32)
+    return workloads.Workload("small", reqs, keys, kb, buf, seed)
+
+
+@pytest.mark.parametrize("nb,wg", [(1, 256), (2, 1024), (4, 256), (4, 512)])
+@pytest.mark.parametrize("op", [workloads.OP_CBC_DEC, workloads.OP_CTR])
+def test_units_shorter_than_a_step(fresh, nb, wg, op):
+    """Requests shorter than a tile's step on several tile shapes: each is one
+    unit, the first starts at offset 0, and a CBC request's only unit takes
+    its IV from the record (never from the bytes before it), out of place and
+    in place."""
+    print(f"[gpu] relaunch: units shorter than a step nb={nb} wg={wg} op={op}", flush=True)
+    fresh.set_config(ctr_nb=nb, ctr_wg=wg, dec_nb=nb, dec_wg=wg, fuse=0)
+    wl = small_requests(op, seed=40 + nb + wg)
+    inp = wl.data()
+    for inplace in (False, True):
+        check(run_gpu(fresh, wl, inp, form="plan", inplace=inplace),
+              run_oracle(wl, inp, inplace=inplace), f"inplace={inplace}")
