@@ -16,16 +16,19 @@ static_assert(TILE_CTRS == 65536, "one counter per workgroup of the largest grid
 constexpr uint32_t TILE_MAX_GRID = TILE_CTRS;
 
 // One table set in LDS per workgroup.  Workgroup g owns a contiguous range
-// of units; its waves claim them one at a time from the workgroup's counter
-// in wg_ctr.  The SIMD arbiter runs the oldest wave first, so with a fixed
-// share per wave the first waves of each SIMD finished in about half the time
-// of the last and the CUs ran the final third of a launch with one or two
-// waves per SIMD; with claims, favoured waves simply take more units.  Each
-// claim is made one unit ahead, so its latency overlaps the unit before.
-// Every wave ends on exactly one failing claim; the wave whose failing claim
-// is the last (value range + waves - 1) resets the counter, which is zero
-// again when the launch ends, ready for the next launch of the same plan on
-// the same stream (or a replay of a graph holding it).
+// of units.  Wave w starts on unit w of the range without a claim (its record
+// is loaded, and its first claim issued, while the tables fill); after that,
+// waves claim units wpb, wpb + 1, ... of the range one at a time from the
+// workgroup's counter in wg_ctr.  The SIMD arbiter runs the oldest wave first,
+// so with a fixed share per wave the first waves of each SIMD finished in
+// about half the time of the last and the CUs ran the final third of a launch
+// with one or two waves per SIMD; with claims, favoured waves simply take
+// more units.  Each claim is made one unit ahead, so its latency overlaps the
+// unit before.  Every wave ends on exactly one failing claim; the wave whose
+// failing claim is the last (value max(range - wpb, 0) + wpb - 1) resets the
+// counter, which is zero again when the launch ends, ready for the next
+// launch of the same plan on the same stream (or a replay of a graph holding
+// it).
 template <bool DEC, int NB, int WG>
 __global__ __launch_bounds__(WG) void k_tiles(const Unit *__restrict__ units, uint32_t n_units,
                                               const aes_schedule_t *__restrict__ sched,
@@ -33,33 +36,39 @@ __global__ __launch_bounds__(WG) void k_tiles(const Unit *__restrict__ units, ui
                                               const uint4 *__restrict__ preds, const uint8_t *in,
                                               uint8_t *out, uint32_t *__restrict__ wg_ctr) {
     __shared__ uint32_t lds[DEC ? LDS_DEC_WORDS : LDS_ENC_WORDS];
-    fill_tables<DEC>(lds, timg);
-    __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t L0 = (lane & 31u) << 2;
-    const uint32_t L2 = L0 | SI_BASE;
     // Waves per workgroup from the template (the kernel is launched with WG
-    // threads); the claimed index is made explicitly uniform, so the unit
-    // record and key-schedule loads stay scalar.
+    // threads); unit indices are made explicitly uniform, so the unit record
+    // and key-schedule loads stay scalar.
     constexpr uint32_t wpb = WG / 64;
     const uint32_t g = blockIdx.x;
     const uint32_t lo = (uint32_t)((uint64_t)n_units * g / gridDim.x);
     const uint32_t range = (uint32_t)((uint64_t)n_units * (g + 1) / gridDim.x) - lo;
     uint32_t *cnt = wg_ctr + g;
+    uint32_t c = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    Unit un;
+    if (c < range)
+        un = units[lo + c];
     uint32_t got = lane == 0 ? atomicAdd(cnt, 1u) : 0u;
-    uint32_t c = __builtin_amdgcn_readfirstlane(got);
+    fill_tables<DEC>(lds, timg);
+    __syncthreads();
+    const uint32_t L0 = (lane & 31u) << 2;
+    const uint32_t L2 = L0 | SI_BASE;
     while (c < range) {
-        got = lane == 0 ? atomicAdd(cnt, 1u) : 0u;  // the next claim, in flight meanwhile
         const uint32_t u = lo + c;
-        const Unit un = units[u];
         if (DEC)
             run_dec_unit<NB, TILE_NV_DEC>(lds, L0, L2, lane, un, preds ? preds + u : nullptr,
                                           sched, n_sched, in, out);
         else
             run_ctr_unit<NB, TILE_NV_CTR>(lds, L0, lane, un, sched, n_sched, in, out, timg);
-        c = __builtin_amdgcn_readfirstlane(got);
+        c = wpb + __builtin_amdgcn_readfirstlane(got);
+        if (c < range) {
+            got = lane == 0 ? atomicAdd(cnt, 1u) : 0u;  // the next claim, in flight meanwhile
+            un = units[lo + c];
+        }
     }
-    if (c == range + wpb - 1 && lane == 0)
+    const uint32_t last = (range > wpb ? range - wpb : 0u) + wpb - 1u;
+    if (__builtin_amdgcn_readfirstlane(got) == last && lane == 0)
         __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
