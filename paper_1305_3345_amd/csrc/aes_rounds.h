@@ -176,16 +176,32 @@ __device__ __forceinline__ void dec_last(const uint32_t *lds, const uint32_t s[4
 
 // ------------------------------------------------------------ block I/O
 
+// A 16-byte vector for the nontemporal builtins (which take no HIP vector
+// types).
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
 // Loads block b of a unit of nbytes bytes; bytes past the end read as zero.
+// NT: whole blocks are read with the nontemporal hint (streamed, not kept in
+// the caches).
+template <bool NT = false>
 __device__ __forceinline__ void load_block(const uint8_t *src, uint32_t b, uint32_t nbytes,
                                            uint32_t x[4]) {
     const uint32_t start = b << 4;
     if (start + 16u <= nbytes) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(src + start);
-        x[0] = v.x;
-        x[1] = v.y;
-        x[2] = v.z;
-        x[3] = v.w;
+        if (NT) {
+            const u32x4_t v =
+                __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(src + start));
+            x[0] = v.x;
+            x[1] = v.y;
+            x[2] = v.z;
+            x[3] = v.w;
+        } else {
+            const uint4 v = *reinterpret_cast<const uint4 *>(src + start);
+            x[0] = v.x;
+            x[1] = v.y;
+            x[2] = v.z;
+            x[3] = v.w;
+        }
     } else {
         x[0] = x[1] = x[2] = x[3] = 0u;
         if (start < nbytes) {
@@ -195,11 +211,17 @@ __device__ __forceinline__ void load_block(const uint8_t *src, uint32_t b, uint3
     }
 }
 
+template <bool NT = false>
 __device__ __forceinline__ void store_block(uint8_t *dst, uint32_t b, uint32_t nbytes,
                                             const uint32_t o[4]) {
     const uint32_t start = b << 4;
     if (start + 16u <= nbytes) {
-        *reinterpret_cast<uint4 *>(dst + start) = make_uint4(o[0], o[1], o[2], o[3]);
+        if (NT) {
+            const u32x4_t v = {o[0], o[1], o[2], o[3]};
+            __builtin_nontemporal_store(v, reinterpret_cast<u32x4_t *>(dst + start));
+        } else {
+            *reinterpret_cast<uint4 *>(dst + start) = make_uint4(o[0], o[1], o[2], o[3]);
+        }
     } else if (start < nbytes) {
         for (uint32_t k = 0; k < nbytes - start; k++)
             dst[start + k] = (uint8_t)(o[k >> 2] >> (8 * (k & 3)));
@@ -518,8 +540,9 @@ __device__ __forceinline__ uint32_t shift_up(uint32_t old, uint32_t v) {
 // SP 800-38A 6.2: P_j = D(C_j) ^ C_(j-1).  Lane l of step i decrypts block
 // 64i + l; its predecessor is lane l-1's ciphertext, and lane 0 takes lane 63
 // of the previous step (or the block before the unit).  ECB (6.1): P_j =
-// D(C_j), no chaining.
-template <int NB, int NR, bool ECB = false, int NV = 0>
+// D(C_j), no chaining.  NT: payload loads and stores with the nontemporal
+// hint.
+template <int NB, int NR, bool ECB = false, int NV = 0, bool NT = false>
 __device__ __forceinline__ void cbcdec_unit(const uint32_t *lds, uint32_t L0,
                                             uint32_t L2, uint32_t lane, const Unit &un,
                                             const uint4 *snap, const uint32_t *__restrict__ dk,
@@ -551,7 +574,7 @@ __device__ __forceinline__ void cbcdec_unit(const uint32_t *lds, uint32_t L0,
         uint32_t c[NB][4], s[NB][4], pred[NB][4];
 #pragma unroll
         for (int i = 0; i < NB; i++)
-            load_block(src, base + 64u * i + lane, nbytes, c[i]);
+            load_block<NT>(src, base + 64u * i + lane, nbytes, c[i]);
 #pragma unroll
         for (int i = 0; i < NB; i++) {
 #pragma unroll
@@ -582,12 +605,12 @@ __device__ __forceinline__ void cbcdec_unit(const uint32_t *lds, uint32_t L0,
         for (int i = 0; i < NB; i++) {
             uint32_t o[4];
             dec_last(lds, s[i], K[NR], L2, pred[i], o);
-            store_block(dst, base + 64u * i + lane, nbytes, o);
+            store_block<NT>(dst, base + 64u * i + lane, nbytes, o);
         }
     }
 }
 
-template <int NB, int NV = 0>
+template <int NB, int NV = 0, bool NT = false>
 __device__ __forceinline__ void run_dec_unit(const uint32_t *lds, uint32_t L0,
                                              uint32_t L2, uint32_t lane, const Unit &un,
                                              const uint4 *snap,
@@ -600,19 +623,19 @@ __device__ __forceinline__ void run_dec_unit(const uint32_t *lds, uint32_t L0,
     const uint32_t nr = ks->nr;
     if (unit_op(un.meta) == AES_OP_ECB_DEC) {
         if (nr == 10)
-            cbcdec_unit<NB, 10, true, NV>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
+            cbcdec_unit<NB, 10, true, NV, NT>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
         else if (nr == 12)
-            cbcdec_unit<NB, 12, true, NV>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
+            cbcdec_unit<NB, 12, true, NV, NT>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
         else if (nr == 14)
-            cbcdec_unit<NB, 14, true, NV>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
+            cbcdec_unit<NB, 14, true, NV, NT>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
         return;
     }
     if (nr == 10)
-        cbcdec_unit<NB, 10, false, NV>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
+        cbcdec_unit<NB, 10, false, NV, NT>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
     else if (nr == 12)
-        cbcdec_unit<NB, 12, false, NV>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
+        cbcdec_unit<NB, 12, false, NV, NT>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
     else if (nr == 14)
-        cbcdec_unit<NB, 14, false, NV>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
+        cbcdec_unit<NB, 14, false, NV, NT>(lds, L0, L2, lane, un, snap, ks->dk, in, out);
 }
 
 }  // namespace aesgpu

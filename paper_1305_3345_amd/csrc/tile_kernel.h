@@ -57,8 +57,9 @@ __global__ __launch_bounds__(WG) void k_tiles(const Unit *__restrict__ units, ui
     while (c < range) {
         const uint32_t u = lo + c;
         if (DEC)
-            run_dec_unit<NB, TILE_NV_DEC>(lds, L0, L2, lane, un, preds ? preds + u : nullptr,
-                                          sched, n_sched, in, out);
+            run_dec_unit<NB, TILE_NV_DEC, true>(lds, L0, L2, lane, un,
+                                                preds ? preds + u : nullptr, sched, n_sched,
+                                                in, out);
         else
             run_ctr_unit<NB, TILE_NV_CTR>(lds, L0, lane, un, sched, n_sched, in, out, timg);
         c = wpb + __builtin_amdgcn_readfirstlane(got);
