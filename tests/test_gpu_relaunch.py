@@ -5,8 +5,10 @@ the same work many times, with eager GPU work between the launches, and check
 every output against the CPU oracle byte for byte: plans relaunched on the
 default grid, on a grid of 24 and one of 20 workgroups, with unit counts that
 do not divide evenly between them; single calls of varying sizes and both
-tile sides in turn on one stream; and in-place CBC decryption relaunched on
-its own output."""
+tile sides in turn on one stream; in-place CBC decryption relaunched on its
+own output; and requests shorter than a tile's step (one unit each, so some
+waves of a workgroup start with no unit of their own) on several tile
+shapes."""
 import numpy as np
 import pytest
 import torch
