@@ -293,10 +293,17 @@ __device__ __forceinline__ void run_chains_quad(const uint32_t *lds, uint32_t L0
     const bool ok = nr == 10 || nr == 12 || nr == 14;
     const uint64_t m12 = __ballot(ok && nr == 12);
     const uint64_t m14 = __ballot(ok && nr == 14);
+    const uint64_t mok = __ballot(ok);
     if (!ok)
         return;
-    if (m14)
+    // A wave whose chains all have the largest round count runs it as a
+    // constant (no selects before the last round).
+    if (m14 == mok)
+        chain_quad_run<14>(lds, L0, q, un, ks->ek, 14u, in, out);
+    else if (m14)
         chain_quad_run<14>(lds, L0, q, un, ks->ek, nr, in, out);
+    else if (m12 == mok)
+        chain_quad_run<12>(lds, L0, q, un, ks->ek, 12u, in, out);
     else if (m12)
         chain_quad_run<12>(lds, L0, q, un, ks->ek, nr, in, out);
     else
