@@ -271,8 +271,11 @@ struct RoundKeys {
 // and side than all-scalar keys with their spills.  CTR tiles with shared
 // heads hold rounds 3..7 (rounds 1 and 2 come from the heads); they spill
 // some loop state to VGPR lanes, read back once per step, and 5 measured
-// ahead of 3 and 4.
+// ahead of 3 and 4.  AES-256 CTR tiles with shared heads hold rounds 3..10
+// (TILE_NV_CTR256): the scalar registers this frees keep a counter group's
+// heads live across its steps.
 constexpr int TILE_NV_CTR = 5;
+constexpr int TILE_NV_CTR256 = 8;
 constexpr int TILE_NV_DEC = 8;
 
 // -------------------------------------------------------------- CTR tiles
@@ -414,12 +417,12 @@ __device__ __forceinline__ void ctr_head_step(const uint32_t *lds, uint32_t L0, 
     }
 }
 
-// ctr_unit with rounds 1 and 2 from the shared heads (same output).  AES-128
-// and AES-192 compute the heads once per group of 256 counters (a 4 KiB
-// unit: once); AES-256 once per step, in a single loop: with the heads live
-// across steps its scalar round keys no longer fit beside them, and the
-// nested loop measured 10% slower than the per-step form, which is 4%
-// faster than no heads at all.
+// ctr_unit with rounds 1 and 2 from the shared heads (same output), computed
+// once per group of 256 counters (a 4 KiB unit: once).  For AES-256 this
+// needs its round keys 3..10 in vector registers (TILE_NV_CTR256): with keys
+// 8..14 in scalar registers the heads live across steps pushed them to VGPR
+// lanes and the form ran 10% slower than computing the heads once per step,
+// which it now beats by 1.2-1.6%.
 template <int NB, int NR, int NV = 0>
 __device__ __forceinline__ void ctr_unit_head(const uint32_t *lds, uint32_t L0, uint32_t lane,
                                               const Unit &un, const uint32_t *__restrict__ rk,
@@ -435,23 +438,14 @@ __device__ __forceinline__ void ctr_unit_head(const uint32_t *lds, uint32_t L0, 
     const uint8_t *src = in + un.off;
     uint8_t *dst = out + un.off;
     uint32_t A[5], D[5];
-    if constexpr (NR <= 12) {
-        for (uint32_t g = 0; g < nblk; g += 256u) {
-            const uint64_t cf = ctr0 + g;  // the group's first counter (wave-uniform)
-            const uint32_t gend = nblk - g < 256u ? nblk : g + 256u;
-            ctr_heads(te, n0, n1, cf, gend - g, rk, A, D);
-            for (uint32_t base = g; base < gend; base += 64u * NB)
-                ctr_head_step<NB, NR, NV>(lds, L0, lane, K, A, D,
-                                          ((uint32_t)cf & 255u) + (base - g), rk[3], base,
-                                          nbytes, src, dst);
-        }
-    } else {
-        for (uint32_t base = 0; base < nblk; base += 64u * NB) {
-            const uint64_t cf = ctr0 + base;  // the step's first counter (wave-uniform)
-            ctr_heads(te, n0, n1, cf, 64u * NB, rk, A, D);
-            ctr_head_step<NB, NR, NV>(lds, L0, lane, K, A, D, (uint32_t)cf & 255u, rk[3], base,
-                                      nbytes, src, dst);
-        }
+    for (uint32_t g = 0; g < nblk; g += 256u) {
+        const uint64_t cf = ctr0 + g;  // the group's first counter (wave-uniform)
+        const uint32_t gend = nblk - g < 256u ? nblk : g + 256u;
+        ctr_heads(te, n0, n1, cf, gend - g, rk, A, D);
+        for (uint32_t base = g; base < gend; base += 64u * NB)
+            ctr_head_step<NB, NR, NV>(lds, L0, lane, K, A, D,
+                                      ((uint32_t)cf & 255u) + (base - g), rk[3], base, nbytes,
+                                      src, dst);
     }
 }
 
@@ -519,7 +513,8 @@ __device__ __forceinline__ void run_ctr_unit(const uint32_t *lds, uint32_t L0,
         else if (nr == 12)
             ctr_unit_head<NB, 12, NV>(lds, L0, lane, un, ks->ek, te, in, out);
         else if (nr == 14)
-            ctr_unit_head<NB, 14, NV>(lds, L0, lane, un, ks->ek, te, in, out);
+            ctr_unit_head<NB, 14, (NV > 0 ? TILE_NV_CTR256 : 0)>(lds, L0, lane, un, ks->ek, te,
+                                                                  in, out);
         return;
     }
     if (nr == 10)
