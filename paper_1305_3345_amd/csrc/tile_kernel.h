@@ -14,6 +14,14 @@ namespace aesgpu {
 // Tile counters: one per workgroup of a tile launch, for each side.
 static_assert(TILE_CTRS == 65536, "one counter per workgroup of the largest grid");
 constexpr uint32_t TILE_MAX_GRID = TILE_CTRS;
+// Grids of up to TILE_SPREAD_GRID workgroups keep each counter on a 128-byte
+// line of its own (word 32 g): with the counters packed, 16 workgroups of all
+// eight XCDs shared each 64-byte line, and the claims of some XCDs were served
+// slower than others' (the slowest XCD's workgroups ended about 4% after the
+// average, launch after launch; with a line each, about 2%), and a launch ends
+// with its slowest workgroup.  Larger grids pack the counters (word g).
+constexpr uint32_t TILE_CTR_STRIDE = 32;
+constexpr uint32_t TILE_SPREAD_GRID = TILE_CTRS / TILE_CTR_STRIDE;
 
 // One table set in LDS per workgroup.  Workgroup g owns a contiguous range
 // of units.  Wave w starts on unit w of the range without a claim (its record
@@ -24,7 +32,8 @@ constexpr uint32_t TILE_MAX_GRID = TILE_CTRS;
 // about half the time of the last and the CUs ran the final third of a launch
 // with one or two waves per SIMD; with claims, favoured waves simply take
 // more units.  Each claim is made one unit ahead, so its latency overlaps the
-// unit before.  Every wave ends on exactly one failing claim; the wave whose
+// unit before (the counters are spread over 128-byte lines, see
+// TILE_CTR_STRIDE).  Every wave ends on exactly one failing claim; the wave whose
 // failing claim is the last (value max(range - wpb, 0) + wpb - 1) resets the
 // counter, which is zero again when the launch ends, ready for the next
 // launch of the same plan on the same stream (or a replay of a graph holding
@@ -44,7 +53,7 @@ __global__ __launch_bounds__(WG) void k_tiles(const Unit *__restrict__ units, ui
     const uint32_t g = blockIdx.x;
     const uint32_t lo = (uint32_t)((uint64_t)n_units * g / gridDim.x);
     const uint32_t range = (uint32_t)((uint64_t)n_units * (g + 1) / gridDim.x) - lo;
-    uint32_t *cnt = wg_ctr + g;
+    uint32_t *cnt = wg_ctr + (gridDim.x <= TILE_SPREAD_GRID ? g * TILE_CTR_STRIDE : g);
     uint32_t c = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     Unit un;
     if (c < range)

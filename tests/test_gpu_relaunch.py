@@ -6,9 +6,10 @@ every output against the CPU oracle byte for byte: plans relaunched on the
 default grid, on a grid of 24 and one of 20 workgroups, with unit counts that
 do not divide evenly between them; single calls of varying sizes and both
 tile sides in turn on one stream; in-place CBC decryption relaunched on its
-own output; and requests shorter than a tile's step (one unit each, so some
+own output; requests shorter than a tile's step (one unit each, so some
 waves of a workgroup start with no unit of their own) on several tile
-shapes."""
+shapes; and a grid of more workgroups than the counters can give a 128-byte
+line each."""
 import numpy as np
 import pytest
 import torch
@@ -140,3 +141,30 @@ def test_units_shorter_than_a_step(fresh, nb, wg, op):
     for inplace in (False, True):
         check(run_gpu(fresh, wl, inp, form="plan", inplace=inplace),
               run_oracle(wl, inp, inplace=inplace), f"inplace={inplace}")
+
+
+@pytest.mark.parametrize("op,bits", [(workloads.OP_CTR, 256), (workloads.OP_CBC_DEC, 128)])
+def test_grid_beyond_spread_counters(fresh, op, bits):
+    """A grid of more than 2,048 workgroups (3,072 of 256 threads), whose
+    counters are packed one word apart instead of one per 128-byte line,
+    relaunched; every launch checked."""
+    print(f"[gpu] relaunch: 3,072-workgroup grid op={op} bits={bits}", flush=True)
+    a = ag()
+    fresh.set_config(ctr_nb=2, ctr_wg=256, dec_nb=2, dec_wg=256, grid=3072)
+    wl = workloads.pages(12289, op, bits, 16, seed=50 + bits)
+    inp = wl.data()
+    want = run_oracle(wl, inp)
+    d_s = device_schedules(wl)
+    d_in = torch.from_numpy(inp).cuda()
+    sentinel = torch.from_numpy(workloads.sentinel(inp.size)).cuda()
+    d_out = sentinel.clone()
+    plan = a.Plan(fresh, wl.reqs, wl.keys.shape[0], wl.buf_bytes)
+    try:
+        for rep in range(4):
+            d_out.copy_(sentinel)
+            torch.cuda.synchronize()
+            plan.launch(d_s, d_in, d_out)
+            torch.cuda.synchronize()
+            check(d_out.cpu().numpy(), want, f"launch {rep}")
+    finally:
+        plan.close()
